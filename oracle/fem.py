@@ -166,7 +166,7 @@ def outward_normals(topo: Topology, faces_idx):
     return nrm
 
 
-def planewave_face_load(xyz, tri, normals, k, d, p, q=8):
+def planewave_face_load(xyz, tri, normals, k, d, p, q=12):
     """f_(i,j) contribution - int_t (l_i g_j - l_j g_i) . g_inc dS for each
     boundary face, g_inc = n x curl E_inc - jk E_inc,t,
     curl E_inc = -jk (d x p) exp(-jk d.r).  Returns [n_f, 3] (TRI_EDGES order).
@@ -239,7 +239,7 @@ class GlobalFEM:
         S.sum_duplicates()
         return S
 
-    def planewave_rhs(self, dirs, pols, q=8):
+    def planewave_rhs(self, dirs, pols, q=12):
         """f [nrhs, n_edges] for plane waves (rows = right-hand sides)."""
         t = self.topo
         dirs = np.atleast_2d(dirs)

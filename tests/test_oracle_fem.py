@@ -124,11 +124,12 @@ def test_free_space_converges_to_plane_wave():
 
 
 def test_planewave_load_quadrature_converged():
-    F = _global(2, k=4 * math.pi)
+    # k h = 1.05 is the coarsest resolution of the standard workloads
+    F = _global(6, k=2 * math.pi)
     d = np.array([0.0, 0.6, 0.8]); p = np.array([1.0, 0.0, 0.0])
-    f8 = F.planewave_rhs(d[None], p[None], q=8)
-    f20 = F.planewave_rhs(d[None], p[None], q=20)
-    assert np.abs(f8 - f20).max() <= 1e-12 * np.abs(f20).max()
+    f12 = F.planewave_rhs(d[None], p[None])
+    f24 = F.planewave_rhs(d[None], p[None], q=24)
+    assert np.abs(f12 - f24).max() <= 1e-13 * np.abs(f24).max()
 
 
 def test_whitney_interpolation_of_constants():
