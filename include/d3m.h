@@ -1,0 +1,233 @@
+/*
+ * d3m.h -- C ABI of the MI355X D3M factor/solve library (libd3m.so).
+ *
+ * Method: Moshfegh & Vouvakis, "Direct Domain Decomposition Method (D3M) for
+ * Finite Element Electromagnetic Computations" (ICEAA 2016).  The library
+ * discretises the decomposed boundary-value problem of Section II with
+ * lowest-order Nedelec (Whitney) edge elements and a first-order absorbing
+ * boundary, couples box subdomains by one set of Robin-type Lagrange
+ * multipliers (eq. (1)), and solves the saddle system by
+ *   step 1  dense domain matrices K_D^(d) = D_d^T A_d^{-1} D_d,
+ *   step 2  assembly of the block-wise sparse reduced matrix K,
+ *   steps 3-4 nested-dissection ordering and block symbolic factorisation,
+ *   step 5  block LDL^T of K with Bunch-Kaufman pivoting restricted to each
+ *           diagonal block (Algorithm 1),
+ *   steps 6-7 forward/diagonal/backward substitution and recovery of E.
+ * Steps 1, 2, 5, 6 and 7 run on the GPU; steps 3-4 and the FEM assembly run
+ * on the host inside d3m_setup.
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) pairs of doubles, the layout
+ *     of C99 double _Complex and of a torch.complex128 tensor.
+ *   - All matrices are complex symmetric (A^T = A, never conjugated).
+ *   - Time convention e^{+j omega t}; incident plane wave p exp(-jk d.r).
+ *   - Every function returns D3M_OK (0) or a negative status; the message of
+ *     the last failure on the calling thread is d3m_last_error().
+ *   - Functions taking a `stream` accept a hipStream_t (NULL = default
+ *     stream).  They enqueue their GPU work on that stream and return after
+ *     it has completed unless stated otherwise.
+ *   - Buffers passed to d3m_solve / d3m_adjoint may live in host memory or in
+ *     device memory of the current device; the library inspects the pointer
+ *     (hipPointerGetAttributes).  Caller keeps ownership of all buffers.
+ */
+#ifndef D3M_H
+#define D3M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define D3M_OK          0
+#define D3M_EINVAL     -1  /* invalid argument, mesh or partition            */
+#define D3M_ESINGULAR  -2  /* a restricted pivot block has a zero column     */
+#define D3M_ENOMEM     -3  /* device or host allocation failed               */
+#define D3M_EHIP       -4  /* a HIP runtime call failed                      */
+#define D3M_ESTATE     -5  /* call out of order (e.g. solve before factor)   */
+#define D3M_ENOCONV    -6  /* iterative refinement missed its tolerance      */
+#define D3M_ENODEV     -7  /* no usable HIP device                           */
+
+/* ---- factorisation precisions ------------------------------------------ */
+#define D3M_FP64       0   /* complex128 everywhere                          */
+#define D3M_FP32_IR    1   /* complex64 factor and sweeps (Bunch-Kaufman
+                              pivot choice, 2x2 inverses and D in FP64) plus
+                              FP64 iterative refinement on the global system */
+
+typedef struct { double re, im; } d3m_c128;
+
+typedef struct d3m_problem *d3m_handle;
+
+/* Tetrahedral mesh.  xyz: [n_vertices][3] row-major; tets: [n_tets][4],
+ * 0-based vertex ids (any vertex order; the library sorts each tetrahedron so
+ * every local edge points from the lower to the higher global vertex id). */
+typedef struct {
+    int64_t n_vertices;
+    const double *xyz;
+    int64_t n_tets;
+    const int64_t *tets;
+} d3m_mesh;
+
+typedef struct {
+    int32_t host_only;    /* 1: d3m_setup stops before any HIP call; only the
+                             host products (d3m_debug_export) are available  */
+    int32_t quad_points;  /* Gauss points per direction of the collapsed
+                             triangle rule for the plane-wave load (default 12) */
+    int32_t ir_max_iter;  /* FP32_IR: maximum refinement steps (default 10)  */
+    int32_t profile;      /* 1: time every kernel launch with HIP events (for
+                             d3m_kernel_stats); adds a little launch overhead */
+    double ir_tol;        /* FP32_IR: stop when max over right-hand sides of
+                             ||f - S E||_inf / ||f||_inf <= ir_tol (1e-10)   */
+    int32_t use_graph;    /* 1: replay each phase from a captured hipGraph  */
+    int32_t device;       /* HIP device ordinal (default 0)                   */
+    int32_t reserved[8];
+} d3m_options;
+
+typedef struct {
+    int64_t n_edges;          /* global unknowns (edges)                     */
+    int64_t n_tets;
+    int32_t n_subdomains;     /* N                                           */
+    int32_t n_blocks;         /* l: blocks (subdomain pairs) of K            */
+    int64_t n_lm;             /* Lagrange multipliers = order of K           */
+    int32_t max_block;        /* largest block order                         */
+    int32_t n_levels;         /* elimination-tree levels of the block graph  */
+    int64_t factor_bytes;     /* device bytes held for the factors           */
+    int64_t device_bytes;     /* all device bytes held by the handle         */
+    double flops_domain;      /* algorithmic flops of step 1 (complex
+                                 multiply-add = 8 flops)                     */
+    double flops_block_ldlt;  /* algorithmic flops of step 5                 */
+    double flops_update_gemm; /* algorithmic flops of all Schur-update GEMMs */
+    double solve_bytes;       /* algorithmic factor bytes read by one solve
+                                 (complex128), excluding vector traffic      */
+    int32_t factored;         /* 0 none, else D3M_FP64 + 1 or D3M_FP32_IR + 1 */
+    int32_t reserved[7];
+} d3m_info;
+
+typedef struct {
+    int32_t iterations;       /* refinement steps taken (0 for FP64)         */
+    int32_t converged;        /* 1 when the residual test passed             */
+    double residual;          /* final max_rhs ||f - S E||_inf / ||f||_inf
+                                 (FP64 evaluation; computed for both modes)   */
+    double copy_discrepancy;  /* max |E_d[e] - E_d'[e]| over shared edges     */
+} d3m_solve_info;
+
+/* Fill `opt` with the defaults listed above. */
+void d3m_default_options(d3m_options *opt);
+
+/* Build the decomposed FEM system (Section II: the BVP, eq. (1); recipe
+ * steps 3-4) on the host and upload it to the device.
+ *   mesh   tetrahedral mesh (copied).
+ *   part   [n_tets] subdomain of each tetrahedron, ids dense in [0, N).
+ *   eps_r  [n_tets] real relative permittivity (mu_r = 1).
+ *   k      free-space wavenumber, > 0.
+ *   alpha  Robin coefficient of the transmission condition (e.g. -jk).
+ *   opt    options (NULL = defaults).
+ * On success *out receives a handle that owns all device memory.
+ * Errors: D3M_EINVAL (degenerate tetrahedron, non-manifold mesh, partition id
+ * out of range, empty subdomain, k <= 0, an edge whose subdomains are not
+ * connected through shared triangles), D3M_ENOMEM, D3M_ENODEV, D3M_EHIP. */
+int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r,
+              double k, d3m_c128 alpha, const d3m_options *opt, d3m_handle *out);
+
+/* Replace eps_r ([n_tets], copied), reassemble the subdomain matrices and
+ * invalidate the factors.  Errors: D3M_EINVAL, D3M_EHIP. */
+int d3m_update_eps(d3m_handle h, const double *eps_r);
+
+/* Recipe steps 1, 2 and 5 on the device (Algorithm 1): dense interior
+ * elimination of every subdomain into its domain matrix, assembly of K, block
+ * LDL^T of K with Bunch-Kaufman pivoting restricted to each diagonal block.
+ * precision: D3M_FP64 or D3M_FP32_IR.  Returns after the stream completes.
+ * Errors: D3M_ESINGULAR (a pivot block is singular; d3m_last_error names the
+ * block and column; there are no delayed pivots), D3M_ENOMEM, D3M_EHIP. */
+int d3m_factor(d3m_handle h, int precision, void *stream);
+
+/* Recipe steps 6-7: E = S^{-1} f for nrhs right-hand sides.
+ *   rhs  [nrhs][n_edges] complex128 (global load f, row per right-hand side).
+ *   E    [nrhs][n_edges] complex128 output.
+ *   info optional diagnostics (NULL allowed).
+ * FP32_IR handles refine in FP64 on the global system until ir_tol.
+ * Errors: D3M_ESTATE (not factored), D3M_EINVAL (nrhs < 1), D3M_ENOCONV
+ * (refinement missed ir_tol; E holds the best iterate), D3M_EHIP. */
+int d3m_solve(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E,
+              d3m_solve_info *info, void *stream);
+
+/* Adjoint of E = S(eps_r)^{-1} f with respect to eps_r, reusing the factors
+ * (S is complex symmetric, so S^{-T} = S^{-1}):
+ *   w = S^{-1} conj(grad_E),  grad_eps[t] = k^2 Re sum_rhs w_t^T M_t E_t,
+ * with M_t the unit-eps_r mass matrix of tetrahedron t.
+ *   grad_E [nrhs][n_edges] dL/dRe E + j dL/dIm E (PyTorch's convention).
+ *   E      [nrhs][n_edges] the forward solution.
+ *   grad_eps [n_tets] real output (overwritten).  w_out optional [nrhs][n_edges].
+ * Errors as for d3m_solve. */
+int d3m_adjoint(d3m_handle h, const d3m_c128 *grad_E, const d3m_c128 *E,
+                int32_t nrhs, double *grad_eps, d3m_c128 *w_out, void *stream);
+
+/* Plane-wave load of the absorbing boundary (second line of the BVP):
+ * f = -oint N . (n x curl E_inc - jk E_inc,t) dS with E_inc = p exp(-jk d.r).
+ *   dirs, pols [nrhs][3] unit propagation directions and polarisations.
+ *   f [nrhs][n_edges] host output.  Works on host-only handles. */
+int d3m_rhs_planewave(d3m_handle h, const double *dirs, const double *pols,
+                      int32_t nrhs, d3m_c128 *f);
+
+/* Whitney field evaluation at points: for point m, E(r_m) = sum_a c[m][a][:] *
+ * u[edge[m][a]] over the six edges of the tetrahedron containing r_m.
+ *   pts [n][3]; edges [n][6] (int64) and coef [n][6][3] (double) host outputs.
+ * Errors: D3M_EINVAL when a point lies outside the mesh. */
+int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges,
+              double *coef);
+
+int d3m_query(d3m_handle h, d3m_info *info);
+void d3m_destroy(d3m_handle h);
+const char *d3m_last_error(void);
+
+/* Per-kernel timings recorded while opt.profile = 1 (reset by this call when
+ * reset != 0).  kernel: 0 update GEMM, 1 panel GEMM, 2 Bunch-Kaufman block,
+ * 3 scatter/assembly, 4 solve sweeps, 5 refinement residual.  Outputs: number
+ * of launches, summed launch milliseconds and algorithmic flops. */
+int d3m_kernel_stats(d3m_handle h, int kernel, int reset, int64_t *launches,
+                     double *total_ms, double *flops);
+
+/* ---- host-side products for parity tests --------------------------------
+ * d3m_debug_export copies one product into a caller-provided host buffer of
+ * `bytes` bytes and returns the number of bytes needed (call with buf = NULL
+ * to size it), or a negative status.  `index` selects a subdomain where
+ * relevant.
+ *   D3M_EXPORT_EDGES     int64 [n_edges][2] global edges (lo, hi)
+ *   D3M_EXPORT_SUB_EDGES int64 [n_d] global edge of each row of subdomain
+ *                        `index` in its elimination order ([interior |
+ *                        interface])
+ *   D3M_EXPORT_SUB_NI    int64 [1] interior edge count of subdomain `index`
+ *   D3M_EXPORT_A_COO     {int64 row, int64 col, double re, double im}[nnz]
+ *                        lower triangle of A_d in the subdomain's order
+ *   D3M_EXPORT_LMS       int64 [n_lm][3] (p, q, edge) in global LM order
+ *   D3M_EXPORT_ORDER     int32 [n_blocks] block (canonical id) eliminated at
+ *                        each position
+ *   D3M_EXPORT_STRUCT    int32 CSR of struct(j) by position: [l+1] offsets
+ *                        followed by the position lists
+ *   D3M_EXPORT_KD        complex128 [m][m] domain matrix K_D^(index) in
+ *                        global-LM order (after d3m_factor, FP64 only)
+ *   D3M_EXPORT_KFACTOR   the factor of -K in elimination-position order:
+ *                        int32 [n_lm] perm-within-block, complex128 [n_lm]
+ *                        D diagonal, complex128 [n_lm] D sub-diagonal, then
+ *                        complex128 dense [n_lm][n_lm] unit lower L
+ *                        (row-major); small problems only
+ *   D3M_EXPORT_LAMBDA    complex128 [nrhs][n_lm] multipliers of the last
+ *                        solve in global LM order                           */
+#define D3M_EXPORT_EDGES      1
+#define D3M_EXPORT_SUB_EDGES  2
+#define D3M_EXPORT_SUB_NI     3
+#define D3M_EXPORT_A_COO      4
+#define D3M_EXPORT_LMS        5
+#define D3M_EXPORT_ORDER      6
+#define D3M_EXPORT_STRUCT     7
+#define D3M_EXPORT_KD         8
+#define D3M_EXPORT_KFACTOR    9
+#define D3M_EXPORT_LAMBDA    10
+int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf,
+                         int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* D3M_H */

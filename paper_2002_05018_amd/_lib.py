@@ -1,0 +1,271 @@
+"""ctypes binding of libd3m.so (names follow include/d3m.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libd3m.so")
+
+if not os.path.exists(library_path):
+    raise ImportError(f"{library_path} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+
+_lib = C.CDLL(library_path)
+
+FP64 = 0
+FP32_IR = 1
+KERNEL_IDS = {"update_gemm": 0, "panel": 1, "bunch_kaufman": 2, "assembly": 3, "solve": 4,
+              "residual": 5}
+
+_STATUS = {0: "D3M_OK", -1: "D3M_EINVAL", -2: "D3M_ESINGULAR", -3: "D3M_ENOMEM",
+           -4: "D3M_EHIP", -5: "D3M_ESTATE", -6: "D3M_ENOCONV", -7: "D3M_ENODEV"}
+
+EXPORT = {"edges": 1, "sub_edges": 2, "sub_ni": 3, "a_coo": 4, "lms": 5, "order": 6,
+          "struct": 7, "kd": 8, "kfactor": 9, "lambda": 10}
+
+# symbols declared in include/d3m.h
+exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_factor",
+                    "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
+                    "d3m_destroy", "d3m_last_error", "d3m_kernel_stats", "d3m_debug_export"]
+
+
+class d3m_c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class d3m_mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)),
+                ("n_tets", C.c_int64), ("tets", C.POINTER(C.c_int64))]
+
+
+class d3m_options(C.Structure):
+    _fields_ = [("host_only", C.c_int32), ("quad_points", C.c_int32),
+                ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
+                ("use_graph", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class d3m_info(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("n_tets", C.c_int64), ("n_subdomains", C.c_int32),
+                ("n_blocks", C.c_int32), ("n_lm", C.c_int64), ("max_block", C.c_int32),
+                ("n_levels", C.c_int32), ("factor_bytes", C.c_int64), ("device_bytes", C.c_int64),
+                ("flops_domain", C.c_double), ("flops_block_ldlt", C.c_double),
+                ("flops_update_gemm", C.c_double), ("solve_bytes", C.c_double),
+                ("factored", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class d3m_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double),
+                ("copy_discrepancy", C.c_double)]
+
+
+_h = C.c_void_p
+_lib.d3m_default_options.argtypes = [C.POINTER(d3m_options)]
+_lib.d3m_default_options.restype = None
+_lib.d3m_setup.argtypes = [C.POINTER(d3m_mesh), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                           C.c_double, d3m_c128, C.POINTER(d3m_options), C.POINTER(_h)]
+_lib.d3m_update_eps.argtypes = [_h, C.POINTER(C.c_double)]
+_lib.d3m_factor.argtypes = [_h, C.c_int, C.c_void_p]
+_lib.d3m_solve.argtypes = [_h, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(d3m_solve_info), C.c_void_p]
+_lib.d3m_adjoint.argtypes = [_h, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.d3m_rhs_planewave.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_void_p]
+_lib.d3m_probe.argtypes = [_h, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+_lib.d3m_query.argtypes = [_h, C.POINTER(d3m_info)]
+_lib.d3m_destroy.argtypes = [_h]
+_lib.d3m_destroy.restype = None
+_lib.d3m_last_error.restype = C.c_char_p
+_lib.d3m_kernel_stats.argtypes = [_h, C.c_int, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
+_lib.d3m_debug_export.argtypes = [_h, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
+_lib.d3m_debug_export.restype = C.c_int64
+for _f in ("d3m_setup", "d3m_update_eps", "d3m_factor", "d3m_solve", "d3m_adjoint",
+           "d3m_rhs_planewave", "d3m_probe", "d3m_query", "d3m_kernel_stats"):
+    getattr(_lib, _f).restype = C.c_int
+
+
+class D3MError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = _STATUS.get(code, str(code))
+
+
+def _check(rc):
+    if rc != 0:
+        raise D3MError(rc, _lib.d3m_last_error().decode())
+    return rc
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """One decomposed problem on the GPU (a d3m_handle)."""
+
+    def __init__(self, xyz, tets, part, eps_r, k, alpha, *, host_only=False, profile=False,
+                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10):
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._tets = np.ascontiguousarray(tets, dtype=np.int64)
+        self._part = np.ascontiguousarray(part, dtype=np.int32)
+        eps = np.ascontiguousarray(eps_r, dtype=np.float64)
+        mesh = d3m_mesh(self._xyz.shape[0], _ptr(self._xyz, C.c_double), self._tets.shape[0],
+                        _ptr(self._tets, C.c_int64))
+        opt = d3m_options()
+        _lib.d3m_default_options(C.byref(opt))
+        opt.host_only = int(host_only)
+        opt.profile = int(profile)
+        opt.device = int(device)
+        opt.quad_points = int(quad_points)
+        opt.ir_tol = float(ir_tol)
+        opt.ir_max_iter = int(ir_max_iter)
+        a = complex(alpha)
+        h = _h()
+        _check(_lib.d3m_setup(C.byref(mesh), _ptr(self._part, C.c_int32), _ptr(eps, C.c_double),
+                              float(k), d3m_c128(a.real, a.imag), C.byref(opt), C.byref(h)))
+        self._handle = h
+        self.k = float(k)
+        self.host_only = bool(host_only)
+        self.info = self.query()
+        self.n_edges = self.info["n_edges"]
+        self.n_tets = self.info["n_tets"]
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls(prob.xyz, prob.tets, prob.part, prob.eps_r, prob.k, prob.alpha, **kw)
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            _lib.d3m_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- steps -------------------------------------------------------------
+    def update_eps(self, eps_r):
+        eps = np.ascontiguousarray(eps_r, dtype=np.float64)
+        _check(_lib.d3m_update_eps(self._handle, _ptr(eps, C.c_double)))
+
+    def factor(self, precision=FP64, stream=None):
+        if isinstance(precision, str):
+            precision = {"fp64": FP64, "fp32_ir": FP32_IR}[precision]
+        _check(_lib.d3m_factor(self._handle, int(precision), _stream_handle(stream)))
+
+    def solve(self, rhs, out=None, stream=None, with_info=False):
+        """E = S^{-1} f for rhs [nrhs, n_edges] complex128 (torch tensor on the
+        GPU or host, or a numpy array)."""
+        import torch
+        if isinstance(rhs, np.ndarray):
+            rhs = torch.from_numpy(np.ascontiguousarray(rhs, dtype=np.complex128))
+        rhs = rhs.contiguous()
+        if rhs.dtype != torch.complex128 or rhs.dim() != 2 or rhs.shape[1] != self.n_edges:
+            raise ValueError("rhs must be complex128 [nrhs, n_edges]")
+        if out is None:
+            out = torch.empty_like(rhs)
+        info = d3m_solve_info()
+        rc = _lib.d3m_solve(self._handle, C.c_void_p(rhs.data_ptr()), rhs.shape[0],
+                            C.c_void_p(out.data_ptr()), C.byref(info) if with_info else None,
+                            _stream_handle(stream) if rhs.is_cuda else C.c_void_p(0))
+        _check(rc)
+        if with_info:
+            return out, {"iterations": info.iterations, "converged": bool(info.converged),
+                         "residual": info.residual}
+        return out
+
+    def adjoint(self, grad_E, E, want_w=False, stream=None):
+        import torch
+        grad_E = grad_E.contiguous()
+        E = E.contiguous()
+        dev = grad_E.device
+        grad = torch.empty(self.n_tets, dtype=torch.float64, device=dev)
+        w = torch.empty_like(grad_E) if want_w else None
+        _check(_lib.d3m_adjoint(self._handle, C.c_void_p(grad_E.data_ptr()), C.c_void_p(E.data_ptr()),
+                                grad_E.shape[0], C.c_void_p(grad.data_ptr()),
+                                C.c_void_p(w.data_ptr()) if w is not None else None,
+                                _stream_handle(stream) if grad_E.is_cuda else C.c_void_p(0)))
+        return (grad, w) if want_w else grad
+
+    def rhs_planewave(self, dirs, pols):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        p = np.ascontiguousarray(np.atleast_2d(pols), dtype=np.float64)
+        f = np.zeros((d.shape[0], self.n_edges), dtype=np.complex128)
+        _check(_lib.d3m_rhs_planewave(self._handle, _ptr(d, C.c_double), _ptr(p, C.c_double), d.shape[0],
+                                      C.c_void_p(f.ctypes.data)))
+        return f
+
+    def probe(self, points):
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        n = pts.shape[0]
+        edges = np.zeros((n, 6), dtype=np.int64)
+        coef = np.zeros((n, 6, 3), dtype=np.float64)
+        _check(_lib.d3m_probe(self._handle, _ptr(pts, C.c_double), n, _ptr(edges, C.c_int64),
+                              _ptr(coef, C.c_double)))
+        return edges, coef
+
+    def query(self):
+        inf = d3m_info()
+        _check(_lib.d3m_query(self._handle, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name != "reserved"}
+
+    def kernel_stats(self, kernel, reset=False):
+        kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel)
+        n = C.c_int64()
+        ms = C.c_double()
+        fl = C.c_double()
+        _check(_lib.d3m_kernel_stats(self._handle, kid, int(reset), C.byref(n), C.byref(ms), C.byref(fl)))
+        return {"launches": n.value, "total_ms": ms.value, "flops": fl.value}
+
+    # ---- host products for parity tests ------------------------------------
+    def export(self, what, index=0):
+        sel = EXPORT[what]
+        nbytes = _lib.d3m_debug_export(self._handle, sel, int(index), None, 0)
+        if nbytes < 0:
+            _check(int(nbytes))
+        buf = np.zeros(int(nbytes), dtype=np.uint8)
+        got = _lib.d3m_debug_export(self._handle, sel, int(index), C.c_void_p(buf.ctypes.data), int(nbytes))
+        if got < 0:
+            _check(int(got))
+        if what in ("edges",):
+            return buf.view(np.int64).reshape(-1, 2)
+        if what in ("sub_edges", "sub_ni"):
+            return buf.view(np.int64)
+        if what == "a_coo":
+            rec = buf.view(np.dtype([("row", "<i8"), ("col", "<i8"), ("re", "<f8"), ("im", "<f8")]))
+            return rec["row"].copy(), rec["col"].copy(), rec["re"] + 1j * rec["im"]
+        if what == "lms":
+            return buf.view(np.int64).reshape(-1, 3)
+        if what == "order":
+            return buf.view(np.int32).copy()
+        if what == "struct":
+            a = buf.view(np.int32)
+            l = self.info["n_blocks"]
+            off = a[:l + 1]
+            lst = a[l + 1:]
+            return [list(lst[off[j]:off[j + 1]]) for j in range(l)]
+        if what == "kd":
+            v = buf.view(np.complex128)
+            m = int(round(np.sqrt(v.size)))
+            return v.reshape(m, m).copy()
+        if what == "kfactor":
+            n = self.info["n_lm"]
+            perm = buf[:4 * n].view(np.int32).copy()
+            rest = buf[4 * n:].view(np.complex128)
+            return perm, rest[:n].copy(), rest[n:2 * n].copy(), rest[2 * n:].reshape(n, n).copy()
+        if what == "lambda":
+            return buf.view(np.complex128).reshape(int(index), -1).copy()
+        return buf

@@ -1,0 +1,30 @@
+"""torch.autograd.Function whose backward pass is the adjoint solve.
+
+Forward: eps_r -> (reassemble A_d, factor, solve) -> E = S(eps_r)^{-1} f.
+Backward: S is complex symmetric, so the adjoint system reuses the same
+factors: w = S^{-1} conj(G) with G = dL/dRe E + j dL/dIm E (PyTorch's
+convention for complex outputs), and dL/d eps_r,t = k^2 Re sum_rhs
+w_t^T M_t E_t (M_t the unit-eps_r element mass), computed by d3m_adjoint.
+The gradient with respect to the load f is conj(w).
+"""
+import torch
+
+
+class D3MSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, eps_r, solver, rhs, precision=0):
+        solver.update_eps(eps_r.detach().cpu().double().numpy())
+        solver.factor(precision)
+        E = solver.solve(rhs.detach())
+        ctx.solver = solver
+        ctx.save_for_backward(E)
+        ctx.rhs_requires_grad = rhs.requires_grad
+        return E
+
+    @staticmethod
+    def backward(ctx, grad_E):
+        (E,) = ctx.saved_tensors
+        solver = ctx.solver
+        grad_eps, w = solver.adjoint(grad_E.contiguous(), E, want_w=True)
+        grad_rhs = torch.conj(w) if ctx.rhs_requires_grad else None
+        return grad_eps.to(torch.float64), None, grad_rhs, None

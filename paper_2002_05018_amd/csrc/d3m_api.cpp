@@ -1,0 +1,859 @@
+// C ABI of the D3M library: handle life cycle, device memory, and the
+// orchestration of the factor (recipe steps 1, 2, 5) and solve (steps 6-7)
+// launch schedules built by the planner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/d3m.h"
+#include "host/plan.hpp"
+#include "host/problem.hpp"
+#include "kernels/launch.hpp"
+
+using namespace d3m;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? D3M_ENOMEM : D3M_EHIP,                            \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                           \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+enum KernelId { KID_UPDATE = 0, KID_PANEL = 1, KID_BK = 2, KID_ASM = 3, KID_SOLVE = 4, KID_RESID = 5, KID_COUNT = 6 };
+
+}  // namespace
+
+struct d3m_problem {
+    Mesh mesh;
+    Decomp dc;
+    BlockOrder bo;
+    Plan pl;
+    double k = 0.0;
+    cplx alpha;
+    std::vector<double> eps;
+    d3m_options opt{};
+    int factored = 0;  // 0 none, 1 fp64, 2 fp32
+    bool device_ready = false;
+    // device: task lists and maps
+    std::vector<DevBuf> bufs;
+    BkTask *d_bk = nullptr;
+    GemmTask *d_gemm = nullptr;
+    GemmPair *d_pairs = nullptr;
+    ScaleTask *d_scale = nullptr;
+    AsmTask *d_asm = nullptr;
+    VDiagTask *d_vdiag = nullptr;
+    VUpdTask *d_vupd = nullptr;
+    VUpdPair *d_vpairs = nullptr;
+    int64_t *d_coo_off = nullptr;
+    double2 *d_coo_val = nullptr;
+    int64_t *d_split = nullptr, *d_collect = nullptr, *d_hmap = nullptr, *d_lmap = nullptr;
+    int *d_status = nullptr;
+    DArrays D{};
+    double2 *d_bkscratch = nullptr;
+    // global FEM matrix for refinement residuals
+    int64_t *d_rowptr = nullptr;
+    int32_t *d_col = nullptr;
+    double2 *d_sval = nullptr;
+    // adjoint data
+    int64_t *d_tet_edges = nullptr;
+    double *d_mass = nullptr;
+    // precision-dependent matrices and vectors
+    DevBuf arr[2][ARR_COUNT];
+    DevBuf vec[2][VARR_COUNT];
+    int vec_nrhs[2] = {0, 0};
+    DevBuf stage_f, stage_E, stage_r, stage_w, stage_g;
+    DevBuf norms;
+    double2 *d_unused = nullptr;
+    // profiling
+    double kstat_ms[KID_COUNT] = {0};
+    int64_t kstat_n[KID_COUNT] = {0};
+    double kstat_flops[KID_COUNT] = {0};
+    std::vector<hipEvent_t> ev_pool;
+    struct Rec { int kid; hipEvent_t a, b; double flops; };
+    std::vector<Rec> recs;
+    size_t ev_next = 0;
+
+    ~d3m_problem() {
+        for (auto &b : bufs) if (b.p) (void)hipFree(b.p);
+        for (int pr = 0; pr < 2; ++pr) {
+            for (auto &b : arr[pr]) if (b.p) (void)hipFree(b.p);
+            for (auto &b : vec[pr]) if (b.p) (void)hipFree(b.p);
+        }
+        for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &norms})
+            if (b->p) (void)hipFree(b->p);
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+    }
+
+    template <typename P>
+    int upload(P *&dst, const void *src, size_t bytes) {
+        DevBuf b;
+        b.bytes = std::max<size_t>(bytes, 16);
+        HIPCHK(hipMalloc(&b.p, b.bytes));
+        bufs.push_back(b);
+        if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        dst = reinterpret_cast<P *>(b.p);
+        return D3M_OK;
+    }
+    template <typename P>
+    int zeros(P *&dst, size_t bytes) {
+        DevBuf b;
+        b.bytes = std::max<size_t>(bytes, 16);
+        HIPCHK(hipMalloc(&b.p, b.bytes));
+        HIPCHK(hipMemset(b.p, 0, b.bytes));
+        bufs.push_back(b);
+        dst = reinterpret_cast<P *>(b.p);
+        return D3M_OK;
+    }
+    int ensure(DevBuf &b, size_t bytes) {
+        if (b.bytes >= bytes && b.p) return D3M_OK;
+        if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+        HIPCHK(hipMalloc(&b.p, std::max<size_t>(bytes, 16)));
+        b.bytes = std::max<size_t>(bytes, 16);
+        return D3M_OK;
+    }
+
+    // ---- profiling helpers
+    void prof_begin(hipEvent_t &a, hipStream_t s) {
+        if (!opt.profile) return;
+        if (ev_next + 2 > ev_pool.size()) {
+            for (int i = 0; i < 256; ++i) { hipEvent_t e; if (hipEventCreate(&e) == hipSuccess) ev_pool.push_back(e); }
+        }
+        a = ev_pool[ev_next++];
+        (void)hipEventRecord(a, s);
+    }
+    void prof_end(int kid, hipEvent_t a, double flops, hipStream_t s) {
+        if (!opt.profile) return;
+        hipEvent_t b = ev_pool[ev_next++];
+        (void)hipEventRecord(b, s);
+        recs.push_back({kid, a, b, flops});
+    }
+    void prof_collect() {
+        if (!opt.profile) return;
+        for (auto &r : recs) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
+            kstat_ms[r.kid] += ms;
+            kstat_n[r.kid] += 1;
+            kstat_flops[r.kid] += r.flops;
+        }
+        recs.clear();
+        ev_next = 0;
+    }
+};
+
+namespace {
+
+void build_global_csr(const Mesh &m, const Decomp &dc, double k, const double *eps, std::vector<int64_t> &rowptr,
+                      std::vector<int32_t> &col, std::vector<double2> &val) {
+    std::vector<std::vector<std::pair<int64_t, cplx>>> rows(m.ne);
+    double Kc[36], M[36], T[9];
+    for (i64 t = 0; t < m.nt; ++t) {
+        tet_curl_mass(m, t, Kc, M);
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b)
+                rows[m.tet_edges[6 * t + a]].push_back(
+                    {m.tet_edges[6 * t + b], cplx(Kc[6 * a + b] - k * k * eps[t] * M[6 * a + b], 0.0)});
+    }
+    for (i64 f : dc.bface) {
+        tri_tangential_mass(m, f, T);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                rows[m.face_edges[3 * f + a]].push_back({m.face_edges[3 * f + b], cplx(0.0, k * T[3 * a + b])});
+    }
+    rowptr.assign(m.ne + 1, 0);
+    col.clear();
+    val.clear();
+    for (i64 r = 0; r < m.ne; ++r) {
+        auto &v = rows[r];
+        std::sort(v.begin(), v.end(), [](auto &x, auto &y) { return x.first < y.first; });
+        for (size_t i = 0; i < v.size();) {
+            size_t j = i;
+            cplx s = 0.0;
+            while (j < v.size() && v[j].first == v[i].first) s += v[j++].second;
+            col.push_back((int32_t)v[i].first);
+            val.push_back(make_double2(s.real(), s.imag()));
+            i = j;
+        }
+        rowptr[r + 1] = (int64_t)col.size();
+        std::vector<std::pair<int64_t, cplx>>().swap(v);
+    }
+}
+
+int setup_device(d3m_problem *h) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(D3M_ENODEV, "no HIP device");
+    if (h->opt.device < 0 || h->opt.device >= ndev) return fail(D3M_ENODEV, "device ordinal out of range");
+    HIPCHK(hipSetDevice(h->opt.device));
+    Plan &pl = h->pl;
+    int rc;
+#define UP(dst, vec) if ((rc = h->upload(dst, vec.data(), vec.size() * sizeof(vec[0]))) != D3M_OK) return rc
+    UP(h->d_bk, pl.bk);
+    UP(h->d_gemm, pl.gemm);
+    UP(h->d_pairs, pl.pairs);
+    UP(h->d_scale, pl.scale);
+    UP(h->d_asm, pl.asmb);
+    UP(h->d_vdiag, pl.vdiag);
+    UP(h->d_vupd, pl.vupd);
+    UP(h->d_vpairs, pl.vpairs);
+    UP(h->d_coo_off, pl.coo_off);
+    UP(h->d_split, pl.split_map);
+    UP(h->d_collect, pl.collect_map);
+    UP(h->d_hmap, pl.h_map);
+    UP(h->d_lmap, pl.lam_map);
+    if ((rc = h->zeros(h->d_status, sizeof(int) * (pl.n_status + 1))) != D3M_OK) return rc;
+    size_t dr = (size_t)std::max<i64>(pl.d_rows, 1);
+    if ((rc = h->zeros(h->D.d, dr * sizeof(double2))) != D3M_OK) return rc;
+    if ((rc = h->zeros(h->D.doff, dr * sizeof(double2))) != D3M_OK) return rc;
+    if ((rc = h->zeros(h->D.dinv, dr * sizeof(double2))) != D3M_OK) return rc;
+    if ((rc = h->zeros(h->D.dinvoff, dr * sizeof(double2))) != D3M_OK) return rc;
+    if ((rc = h->zeros(h->D.piv, dr * sizeof(int))) != D3M_OK) return rc;
+    if ((rc = h->zeros(h->D.perm, dr * sizeof(int))) != D3M_OK) return rc;
+    if (pl.bk_scratch_elems > 0)
+        if ((rc = h->zeros(h->d_bkscratch, (size_t)pl.bk_scratch_elems * sizeof(double2))) != D3M_OK) return rc;
+    // values of the scatter (A_d entries then the +-1 of D_d)
+    {
+        std::vector<double2> v;
+        v.reserve(pl.coo_off.size());
+        for (int d = 0; d < h->dc.N; ++d)
+            for (auto &x : h->dc.sub[d].a_val) v.push_back(make_double2(x.real(), x.imag()));
+        for (int d = 0; d < h->dc.N; ++d) {
+            const Subdomain &S = h->dc.sub[d];
+            for (int P : S.blocks)
+                for (i64 l = h->dc.blk_start[P]; l < h->dc.blk_start[P + 1]; ++l)
+                    v.push_back(make_double2(h->dc.lm_p[l] == d ? 1.0 : -1.0, 0.0));
+        }
+        UP(h->d_coo_val, v);
+    }
+    {
+        std::vector<int64_t> rp;
+        std::vector<int32_t> col;
+        std::vector<double2> val;
+        build_global_csr(h->mesh, h->dc, h->k, h->eps.data(), rp, col, val);
+        UP(h->d_rowptr, rp);
+        UP(h->d_col, col);
+        UP(h->d_sval, val);
+    }
+    {
+        UP(h->d_tet_edges, h->mesh.tet_edges);
+        std::vector<double> mass(36 * h->mesh.nt);
+        double Kc[36];
+        for (i64 t = 0; t < h->mesh.nt; ++t) tet_curl_mass(h->mesh, t, Kc, &mass[36 * t]);
+        UP(h->d_mass, mass);
+    }
+#undef UP
+    HIPCHK(hipDeviceSynchronize());
+    h->device_ready = true;
+    return D3M_OK;
+}
+
+template <typename T>
+int ensure_arrays(d3m_problem *h) {
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    const size_t es = sizeof(T) * 2;
+    const Plan &pl = h->pl;
+    const i64 tiles[ARR_COUNT] = {pl.m_tiles, pl.m_tiles, pl.k_tiles, pl.k_tiles, pl.k_tiles, pl.tt_tiles};
+    for (int a = 0; a < ARR_COUNT; ++a) {
+        int rc = h->ensure(h->arr[pr][a], (size_t)tiles[a] * TILE_ELEMS * es);
+        if (rc != D3M_OK) return rc;
+    }
+    return D3M_OK;
+}
+
+template <typename T>
+Bases bases_of(d3m_problem *h) {
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    Bases b;
+    for (int a = 0; a < ARR_COUNT; ++a) b.p[a] = h->arr[pr][a].p;
+    return b;
+}
+
+template <typename T>
+int ensure_vectors(d3m_problem *h, int nrhs) {
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    if (h->vec_nrhs[pr] >= nrhs) return D3M_OK;
+    const size_t es = sizeof(T) * 2;
+    const Plan &pl = h->pl;
+    for (int v = 0; v < VARR_COUNT; ++v) {
+        i64 tiles = v < V_KX ? pl.v_tiles_s1 : pl.v_tiles_k;
+        int rc = h->ensure(h->vec[pr][v], (size_t)std::max<i64>(tiles, 1) * 64 * nrhs * es);
+        if (rc != D3M_OK) return rc;
+    }
+    h->vec_nrhs[pr] = nrhs;
+    return D3M_OK;
+}
+
+template <typename T>
+VBases vbases_of(d3m_problem *h) {
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    VBases b;
+    for (int v = 0; v < VARR_COUNT; ++v) b.p[v] = h->vec[pr][v].p;
+    return b;
+}
+
+template <typename T>
+int run_factor_step(d3m_problem *h, const FactorStep &st, const Bases &b, hipStream_t s) {
+    hipEvent_t ev{};
+    h->prof_begin(ev, s);
+    HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
+    h->prof_end(KID_BK, ev, 0.0, s);
+    h->prof_begin(ev, s);
+    HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+    HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+    h->prof_end(KID_PANEL, ev, st.pan_flops, s);
+    h->prof_begin(ev, s);
+    HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.nup, h->d_pairs, b, 1, s));
+    h->prof_end(KID_UPDATE, ev, st.up_flops, s);
+    return D3M_OK;
+}
+
+template <typename T>
+int factor_impl(d3m_problem *h, hipStream_t s) {
+    int rc = ensure_arrays<T>(h);
+    if (rc != D3M_OK) return rc;
+    const Plan &pl = h->pl;
+    Bases b = bases_of<T>(h);
+    hipEvent_t ev{};
+    h->prof_begin(ev, s);
+    HIPCHK(launch_fill_zero<T>(b.p[ARR_M], pl.m_tiles * TILE_ELEMS, s));
+    HIPCHK(launch_coo_scatter<T>(b.p[ARR_M], h->d_coo_off, h->d_coo_val, (int64_t)pl.coo_off.size(), s));
+    HIPCHK(hipMemsetAsync(h->d_status, 0, sizeof(int) * (pl.n_status + 1), s));
+    h->prof_end(KID_ASM, ev, 0.0, s);
+    for (const auto &st : pl.s1_steps)
+        if ((rc = run_factor_step<T>(h, st, b, s)) != D3M_OK) return rc;
+    h->prof_begin(ev, s);
+    HIPCHK(launch_asm<T>(h->d_asm, (int64_t)pl.asmb.size(), b, s));
+    h->prof_end(KID_ASM, ev, 0.0, s);
+    for (const auto &st : pl.k_steps)
+        if ((rc = run_factor_step<T>(h, st, b, s)) != D3M_OK) return rc;
+    std::vector<int> status(pl.n_status + 1, 0);
+    HIPCHK(hipMemcpyAsync(status.data(), h->d_status, sizeof(int) * status.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->prof_collect();
+    for (int i = 0; i < pl.n_status; ++i)
+        if (status[i] != 0) {
+            const BkTask &t = pl.bk[i];
+            std::string where;
+            const i64 first_k = pl.k_steps.empty() ? (i64)pl.bk.size() : pl.k_steps[0].bk0;
+            if (i < first_k) {
+                where = "subdomain diagonal tile (task " + std::to_string(i) + ")";
+            } else {
+                int pos = -1;
+                for (size_t j = 0; j < pl.drow_k.size(); ++j) if (pl.drow_k[j] == t.drow) pos = (int)j;
+                where = "block at position " + std::to_string(pos) + " (canonical " +
+                        std::to_string(pos >= 0 ? h->bo.order[pos] : -1) + ")";
+            }
+            return fail(D3M_ESINGULAR, "singular pivot block: " + where + ", column " + std::to_string(status[i] - 1));
+        }
+    return D3M_OK;
+}
+
+template <typename T>
+int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases &vb, bool bwd, int nrhs,
+               hipStream_t s) {
+    if (st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
+    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, bwd, b, vb, h->D, nrhs, s));
+    if (!st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
+    return D3M_OK;
+}
+
+// E (=|+=) S^{-1} f through the factors of precision T; f and E on the device
+template <typename T>
+int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
+    int rc = ensure_vectors<T>(h, nrhs);
+    if (rc != D3M_OK) return rc;
+    const Plan &pl = h->pl;
+    Bases b = bases_of<T>(h);
+    VBases vb = vbases_of<T>(h);
+    hipEvent_t ev{};
+    h->prof_begin(ev, s);
+    HIPCHK(launch_vsplit<T>(vb.p[V_X], f, h->d_split, pl.v_tiles_s1 * 64, nrhs, h->mesh.ne, s));
+    for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
+    HIPCHK(launch_vgather_h<T>(vb.p[V_KX], vb.p[V_X], h->d_hmap, pl.v_tiles_k * 64, nrhs, s));
+    for (const auto &st : pl.k_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
+    for (const auto &st : pl.k_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
+    HIPCHK(launch_vscatter_lam<T>(vb.p[V_X], vb.p[V_KX], h->d_lmap, pl.v_tiles_s1 * 64, nrhs, s));
+    for (const auto &st : pl.s1_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
+    HIPCHK(launch_vcollect<T>(E, vb.p[V_X], h->d_collect, h->mesh.ne, nrhs, accumulate, s));
+    h->prof_end(KID_SOLVE, ev, 0.0, s);
+    return D3M_OK;
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+    return a.type == hipMemoryTypeDevice;
+}
+
+int norms_inf(d3m_problem *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t s) {
+    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
+    HIPCHK(launch_rownorm_max((unsigned long long *)h->norms.p, v, h->mesh.ne, nrhs, s));
+    std::vector<unsigned long long> bits(nrhs);
+    HIPCHK(hipMemcpyAsync(bits.data(), h->norms.p, sizeof(unsigned long long) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.resize(nrhs);
+    for (int c = 0; c < nrhs; ++c) std::memcpy(&out[c], &bits[c], sizeof(double));
+    return D3M_OK;
+}
+
+// full solve on device buffers (both precisions); optional diagnostics
+int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_solve_info *info, hipStream_t s) {
+    const size_t vbytes = sizeof(double2) * (size_t)nrhs * h->mesh.ne;
+    int rc;
+    if (h->factored == 1) {
+        if ((rc = solve_pass<double>(h, f, E, nrhs, false, s))) return rc;
+        if (info) {
+            if ((rc = h->ensure(h->stage_r, vbytes))) return rc;
+            hipEvent_t ev{};
+            h->prof_begin(ev, s);
+            HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
+            h->prof_end(KID_RESID, ev, 0.0, s);
+            std::vector<double> rn, fn;
+            if ((rc = norms_inf(h, (double2 *)h->stage_r.p, nrhs, rn, s))) return rc;
+            if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
+            double res = 0.0;
+            for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
+            info->iterations = 0;
+            info->converged = 1;
+            info->residual = res;
+            info->copy_discrepancy = 0.0;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        h->prof_collect();
+        return D3M_OK;
+    }
+    // FP32 factors with FP64 iterative refinement on S E = f
+    if ((rc = h->ensure(h->stage_r, vbytes))) return rc;
+    std::vector<double> fn, rn;
+    if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
+    if ((rc = solve_pass<float>(h, f, E, nrhs, false, s))) return rc;
+    int it = 0;
+    double res = 0.0;
+    bool ok = false;
+    for (;;) {
+        hipEvent_t ev{};
+        h->prof_begin(ev, s);
+        HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
+        h->prof_end(KID_RESID, ev, 0.0, s);
+        if ((rc = norms_inf(h, (double2 *)h->stage_r.p, nrhs, rn, s))) return rc;
+        res = 0.0;
+        for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
+        if (res <= h->opt.ir_tol) { ok = true; break; }
+        if (it >= h->opt.ir_max_iter) break;
+        if ((rc = solve_pass<float>(h, (double2 *)h->stage_r.p, E, nrhs, true, s))) return rc;
+        ++it;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    h->prof_collect();
+    if (info) {
+        info->iterations = it;
+        info->converged = ok ? 1 : 0;
+        info->residual = res;
+        info->copy_discrepancy = 0.0;
+    }
+    if (!ok) return fail(D3M_ENOCONV, "iterative refinement stopped at relative residual " + std::to_string(res));
+    return D3M_OK;
+}
+
+}  // namespace
+
+// =========================================================== C ABI ======
+extern "C" {
+
+const char *d3m_last_error(void) { return g_err.c_str(); }
+
+void d3m_default_options(d3m_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->quad_points = 12;
+    o->ir_max_iter = 10;
+    o->ir_tol = 1e-10;
+}
+
+int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r, double k, d3m_c128 alpha,
+              const d3m_options *opt, d3m_handle *out) {
+    if (!out) return fail(D3M_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!mesh || !mesh->xyz || !mesh->tets || !part || !eps_r) return fail(D3M_EINVAL, "null argument");
+    std::unique_ptr<d3m_problem> h(new d3m_problem());
+    if (opt) h->opt = *opt; else d3m_default_options(&h->opt);
+    if (h->opt.quad_points <= 0) h->opt.quad_points = 12;
+    if (h->opt.ir_max_iter <= 0 && !opt) h->opt.ir_max_iter = 10;
+    if (!(h->opt.ir_tol > 0)) h->opt.ir_tol = 1e-10;
+    try {
+        build_mesh(h->mesh, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets);
+        h->k = k;
+        h->alpha = cplx(alpha.re, alpha.im);
+        h->eps.assign(eps_r, eps_r + mesh->n_tets);
+        build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
+        order_blocks(h->bo, h->dc, h->mesh);
+        build_plan(h->pl, h->dc, h->bo);
+    } catch (const Error &e) {
+        return fail(D3M_EINVAL, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(D3M_ENOMEM, "host allocation failed in setup");
+    }
+    if (!h->opt.host_only) {
+        int rc = setup_device(h.get());
+        if (rc != D3M_OK) return rc;
+    }
+    *out = h.release();
+    return D3M_OK;
+}
+
+int d3m_update_eps(d3m_handle h, const double *eps_r) {
+    if (!h || !eps_r) return fail(D3M_EINVAL, "null argument");
+    h->eps.assign(eps_r, eps_r + h->mesh.nt);
+    reassemble_values(h->dc, h->mesh, h->k, eps_r);
+    h->factored = 0;
+    if (h->device_ready) {
+        std::vector<double2> v;
+        for (int d = 0; d < h->dc.N; ++d)
+            for (auto &x : h->dc.sub[d].a_val) v.push_back(make_double2(x.real(), x.imag()));
+        HIPCHK(hipMemcpy(h->d_coo_val, v.data(), v.size() * sizeof(double2), hipMemcpyHostToDevice));
+        std::vector<int64_t> rp;
+        std::vector<int32_t> col;
+        std::vector<double2> val;
+        build_global_csr(h->mesh, h->dc, h->k, eps_r, rp, col, val);
+        HIPCHK(hipMemcpy(h->d_sval, val.data(), val.size() * sizeof(double2), hipMemcpyHostToDevice));
+    }
+    return D3M_OK;
+}
+
+int d3m_factor(d3m_handle h, int precision, void *stream) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (!h->device_ready) return fail(D3M_ESTATE, "handle was set up host-only");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->opt.device));
+    int rc;
+    h->factored = 0;
+    if (precision == D3M_FP64) rc = factor_impl<double>(h, s);
+    else if (precision == D3M_FP32_IR) rc = factor_impl<float>(h, s);
+    else return fail(D3M_EINVAL, "unknown precision");
+    if (rc == D3M_OK) h->factored = precision == D3M_FP64 ? 1 : 2;
+    return rc;
+}
+
+int d3m_solve(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E, d3m_solve_info *info, void *stream) {
+    if (!h || !rhs || !E) return fail(D3M_EINVAL, "null argument");
+    if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
+    if (!h->factored) return fail(D3M_ESTATE, "solve before factor");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->opt.device));
+    const size_t bytes = sizeof(double2) * (size_t)nrhs * h->mesh.ne;
+    const double2 *f = reinterpret_cast<const double2 *>(rhs);
+    double2 *e = reinterpret_cast<double2 *>(E);
+    bool fdev = is_device_ptr(rhs), edev = is_device_ptr(E);
+    int rc;
+    if (!fdev) {
+        if ((rc = h->ensure(h->stage_f, bytes))) return rc;
+        HIPCHK(hipMemcpyAsync(h->stage_f.p, rhs, bytes, hipMemcpyHostToDevice, s));
+        f = (const double2 *)h->stage_f.p;
+    }
+    if (!edev) {
+        if ((rc = h->ensure(h->stage_E, bytes))) return rc;
+        e = (double2 *)h->stage_E.p;
+    }
+    rc = solve_device(h, f, e, nrhs, info, s);
+    if (!edev && (rc == D3M_OK || rc == D3M_ENOCONV)) {
+        HIPCHK(hipMemcpyAsync(E, e, bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return rc;
+}
+
+int d3m_adjoint(d3m_handle h, const d3m_c128 *grad_E, const d3m_c128 *E, int32_t nrhs, double *grad_eps,
+                d3m_c128 *w_out, void *stream) {
+    if (!h || !grad_E || !E || !grad_eps) return fail(D3M_EINVAL, "null argument");
+    if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
+    if (!h->factored) return fail(D3M_ESTATE, "adjoint before factor");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->opt.device));
+    const int64_t ne = h->mesh.ne;
+    const size_t bytes = sizeof(double2) * (size_t)nrhs * ne;
+    int rc;
+    const double2 *g = reinterpret_cast<const double2 *>(grad_E);
+    const double2 *ef = reinterpret_cast<const double2 *>(E);
+    if (!is_device_ptr(grad_E)) {
+        if ((rc = h->ensure(h->stage_f, bytes))) return rc;
+        HIPCHK(hipMemcpyAsync(h->stage_f.p, grad_E, bytes, hipMemcpyHostToDevice, s));
+        g = (const double2 *)h->stage_f.p;
+    }
+    if (!is_device_ptr(E)) {
+        if ((rc = h->ensure(h->stage_E, bytes))) return rc;
+        HIPCHK(hipMemcpyAsync(h->stage_E.p, E, bytes, hipMemcpyHostToDevice, s));
+        ef = (const double2 *)h->stage_E.p;
+    }
+    if ((rc = h->ensure(h->stage_g, bytes))) return rc;
+    if ((rc = h->ensure(h->stage_w, bytes))) return rc;
+    HIPCHK(launch_conj((double2 *)h->stage_g.p, g, (int64_t)nrhs * ne, s));
+    rc = solve_device(h, (double2 *)h->stage_g.p, (double2 *)h->stage_w.p, nrhs, nullptr, s);
+    if (rc != D3M_OK) return rc;
+    bool gdev = is_device_ptr(grad_eps);
+    double *gout = grad_eps;
+    DevBuf tmp;
+    if (!gdev) {
+        if ((rc = h->ensure(h->stage_r, sizeof(double) * h->mesh.nt))) return rc;
+        gout = (double *)h->stage_r.p;
+    }
+    HIPCHK(launch_adjoint_grad(gout, (double2 *)h->stage_w.p, ef, h->d_tet_edges, h->d_mass, h->k * h->k,
+                               h->mesh.nt, ne, nrhs, s));
+    if (!gdev) HIPCHK(hipMemcpyAsync(grad_eps, gout, sizeof(double) * h->mesh.nt, hipMemcpyDeviceToHost, s));
+    if (w_out) HIPCHK(hipMemcpyAsync(w_out, h->stage_w.p, bytes, hipMemcpyDefault, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return D3M_OK;
+}
+
+int d3m_rhs_planewave(d3m_handle h, const double *dirs, const double *pols, int32_t nrhs, d3m_c128 *f) {
+    if (!h || !dirs || !pols || !f) return fail(D3M_EINVAL, "null argument");
+    if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
+    std::vector<double> qs, qt, qw;
+    triangle_rule(h->opt.quad_points, qs, qt, qw);
+    const int64_t ne = h->mesh.ne;
+    std::memset(f, 0, sizeof(d3m_c128) * (size_t)nrhs * ne);
+    for (int c = 0; c < nrhs; ++c) {
+        for (i64 fi : h->dc.bface) {
+            cplx out[3];
+            face_planewave_load(h->mesh, fi, h->k, dirs + 3 * c, pols + 3 * c, qs, qt, qw, out);
+            for (int a = 0; a < 3; ++a) {
+                d3m_c128 &x = f[(size_t)c * ne + h->mesh.face_edges[3 * fi + a]];
+                x.re += out[a].real();
+                x.im += out[a].imag();
+            }
+        }
+    }
+    return D3M_OK;
+}
+
+int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges, double *coef) {
+    if (!h || !pts || !edges || !coef) return fail(D3M_EINVAL, "null argument");
+    const Mesh &m = h->mesh;
+    static const int te[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int p = 0; p < n; ++p) {
+        const double *r = pts + 3 * p;
+        i64 best = -1;
+        double bestmin = -1e300, bl[4] = {0, 0, 0, 0};
+        for (i64 t = 0; t < m.nt; ++t) {
+            const double *x0 = &m.xyz[3 * m.tets[4 * t]];
+            const double *g = &m.grads[12 * t];
+            double l[4];
+            double d[3] = {r[0] - x0[0], r[1] - x0[1], r[2] - x0[2]};
+            for (int a = 1; a < 4; ++a) l[a] = g[3 * a] * d[0] + g[3 * a + 1] * d[1] + g[3 * a + 2] * d[2];
+            l[0] = 1.0 - l[1] - l[2] - l[3];
+            double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+            if (mn > bestmin) { bestmin = mn; best = t; std::memcpy(bl, l, sizeof(l)); }
+            if (mn >= 0) break;
+        }
+        if (best < 0 || bestmin < -1e-12) return fail(D3M_EINVAL, "probe point outside the mesh");
+        const double *g = &m.grads[12 * best];
+        for (int a = 0; a < 6; ++a) {
+            int i = te[a][0], j = te[a][1];
+            edges[6 * p + a] = m.tet_edges[6 * best + a];
+            for (int x = 0; x < 3; ++x) coef[18 * p + 3 * a + x] = bl[i] * g[3 * j + x] - bl[j] * g[3 * i + x];
+        }
+    }
+    return D3M_OK;
+}
+
+int d3m_query(d3m_handle h, d3m_info *info) {
+    if (!h || !info) return fail(D3M_EINVAL, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_edges = h->mesh.ne;
+    info->n_tets = h->mesh.nt;
+    info->n_subdomains = h->dc.N;
+    info->n_blocks = h->dc.nblk;
+    info->n_lm = h->dc.n_lm;
+    int mb = 0;
+    for (int b = 0; b < h->dc.nblk; ++b) mb = std::max<int>(mb, (int)(h->dc.blk_start[b + 1] - h->dc.blk_start[b]));
+    info->max_block = mb;
+    info->n_levels = h->bo.n_levels;
+    info->factor_bytes = (int64_t)h->pl.factor_entries * 16;
+    int64_t dev = 0;
+    for (auto &b : h->bufs) dev += (int64_t)b.bytes;
+    for (int pr = 0; pr < 2; ++pr) {
+        for (auto &b : h->arr[pr]) dev += (int64_t)b.bytes;
+        for (auto &b : h->vec[pr]) dev += (int64_t)b.bytes;
+    }
+    info->device_bytes = dev;
+    info->flops_domain = h->pl.flops_s1;
+    info->flops_block_ldlt = h->pl.flops_s3;
+    info->flops_update_gemm = h->pl.flops_update;
+    info->solve_bytes = h->pl.solve_bytes;
+    info->factored = h->factored;
+    return D3M_OK;
+}
+
+void d3m_destroy(d3m_handle h) { delete h; }
+
+int d3m_kernel_stats(d3m_handle h, int kernel, int reset, int64_t *launches, double *total_ms, double *flops) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (kernel < 0 || kernel >= KID_COUNT) return fail(D3M_EINVAL, "unknown kernel id");
+    if (launches) *launches = h->kstat_n[kernel];
+    if (total_ms) *total_ms = h->kstat_ms[kernel];
+    if (flops) *flops = h->kstat_flops[kernel];
+    if (reset) { h->kstat_n[kernel] = 0; h->kstat_ms[kernel] = 0; h->kstat_flops[kernel] = 0; }
+    return D3M_OK;
+}
+
+int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf, int64_t bytes) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    std::vector<char> out;
+    auto put = [&](const void *p, size_t n) {
+        const char *c = (const char *)p;
+        out.insert(out.end(), c, c + n);
+    };
+    const Decomp &dc = h->dc;
+    switch (what) {
+    case D3M_EXPORT_EDGES: put(h->mesh.edges.data(), h->mesh.edges.size() * 8); break;
+    case D3M_EXPORT_SUB_EDGES:
+    case D3M_EXPORT_SUB_NI:
+    case D3M_EXPORT_A_COO: {
+        if (index < 0 || index >= dc.N) return fail(D3M_EINVAL, "subdomain index out of range");
+        const Subdomain &S = dc.sub[index];
+        if (what == D3M_EXPORT_SUB_EDGES) put(S.edges.data(), S.edges.size() * 8);
+        else if (what == D3M_EXPORT_SUB_NI) put(&S.nI, 8);
+        else
+            for (size_t x = 0; x < S.a_row.size(); ++x) {
+                double re = S.a_val[x].real(), im = S.a_val[x].imag();
+                put(&S.a_row[x], 8); put(&S.a_col[x], 8); put(&re, 8); put(&im, 8);
+            }
+        break;
+    }
+    case D3M_EXPORT_LMS:
+        for (i64 l = 0; l < dc.n_lm; ++l) { put(&dc.lm_p[l], 8); put(&dc.lm_q[l], 8); put(&dc.lm_e[l], 8); }
+        break;
+    case D3M_EXPORT_ORDER: put(h->bo.order.data(), h->bo.order.size() * 4); break;
+    case D3M_EXPORT_STRUCT: {
+        std::vector<int32_t> off{0}, lst;
+        for (auto &s : h->bo.strct) { lst.insert(lst.end(), s.begin(), s.end()); off.push_back((int32_t)lst.size()); }
+        put(off.data(), off.size() * 4);
+        put(lst.data(), lst.size() * 4);
+        break;
+    }
+    case D3M_EXPORT_KD: {
+        if (h->factored != 1) return fail(D3M_ESTATE, "K_D export needs an FP64 factorisation");
+        if (index < 0 || index >= dc.N) return fail(D3M_EINVAL, "subdomain index out of range");
+        const Subdomain &S = dc.sub[index];
+        const Plan &pl = h->pl;
+        const i64 m = S.m;
+        std::vector<double2> tiles((size_t)tri_slot(pl.T[index], 0) * TILE_ELEMS);
+        if (hipMemcpy(tiles.data(), (double2 *)h->arr[0][ARR_M].p + pl.m_base[index] * TILE_ELEMS,
+                      tiles.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(D3M_EHIP, "copy of the subdomain tiles failed");
+        for (i64 r = 0; r < m; ++r)
+            for (i64 c = 0; c < m; ++c) {
+                i64 R = (i64)pl.TE[index] * TILE + std::max(r, c), C = (i64)pl.TE[index] * TILE + std::min(r, c);
+                double2 v = tiles[tri_slot(R / TILE, C / TILE) * TILE_ELEMS + (C % TILE) * TILE + R % TILE];
+                double2 kd = make_double2(-v.x, -v.y);  // trailing block = -K_D
+                put(&kd, sizeof(kd));
+            }
+        break;
+    }
+    case D3M_EXPORT_KFACTOR: {
+        if (!h->factored) return fail(D3M_ESTATE, "not factored");
+        const Plan &pl = h->pl;
+        const i64 n = dc.n_lm;
+        if (n > 20000) return fail(D3M_EINVAL, "factor export is for small problems");
+        const int pr = h->factored == 1 ? 0 : 1;
+        const size_t es = pr == 0 ? 16 : 8;
+        std::vector<char> raw(pl.k_tiles * TILE_ELEMS * es);
+        if (hipMemcpy(raw.data(), h->arr[pr][ARR_KL].p, raw.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(D3M_EHIP, "copy of the K factor failed");
+        auto tile_val = [&](i64 slot, int r, int c) -> double2 {
+            size_t idx = (size_t)slot * TILE_ELEMS + (size_t)c * TILE + r;
+            if (pr == 0) return ((double2 *)raw.data())[idx];
+            float2 v = ((float2 *)raw.data())[idx];
+            return make_double2(v.x, v.y);
+        };
+        std::vector<int> perm(pl.d_rows), piv(pl.d_rows);
+        std::vector<double2> dd(pl.d_rows), doff(pl.d_rows);
+        if (hipMemcpy(perm.data(), h->D.perm, pl.d_rows * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(dd.data(), h->D.d, pl.d_rows * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(doff.data(), h->D.doff, pl.d_rows * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(piv.data(), h->D.piv, pl.d_rows * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(D3M_EHIP, "copy of the pivot data failed");
+        const int nb = dc.nblk;
+        std::vector<i64> off(nb + 1, 0);
+        std::vector<int> nsz(nb);
+        for (int j = 0; j < nb; ++j) {
+            int b = h->bo.order[j];
+            nsz[j] = (int)(dc.blk_start[b + 1] - dc.blk_start[b]);
+            off[j + 1] = off[j] + nsz[j];
+        }
+        std::vector<int32_t> pv(n);
+        std::vector<double2> d0(n), d1(n);
+        for (int j = 0; j < nb; ++j)
+            for (int r = 0; r < nsz[j]; ++r) {
+                pv[off[j] + r] = perm[pl.drow_k[j] + r];
+                d0[off[j] + r] = dd[pl.drow_k[j] + r];
+                // sub-diagonal of D: only on the first row of a 2x2 pivot
+                d1[off[j] + r] = piv[pl.drow_k[j] + r] == 1 ? doff[pl.drow_k[j] + r] : make_double2(0, 0);
+            }
+        put(pv.data(), n * 4);
+        put(d0.data(), n * 16);
+        put(d1.data(), n * 16);
+        std::vector<double2> L((size_t)n * n, make_double2(0, 0));
+        for (int j = 0; j < nb; ++j) {
+            std::vector<int> rows{j};
+            rows.insert(rows.end(), h->bo.strct[j].begin(), h->bo.strct[j].end());
+            for (size_t ii = 0; ii < rows.size(); ++ii) {
+                int i = rows[ii];
+                for (int r = 0; r < nsz[i]; ++r)
+                    for (int c = 0; c < nsz[j]; ++c) {
+                        if (i == j && r < c) continue;
+                        i64 slot = pl.kcol[j] + (i64)(c / TILE) * pl.kR[j] + pl.krow_off[j][ii] + r / TILE;
+                        L[(size_t)(off[i] + r) * n + off[j] + c] = tile_val(slot, r % TILE, c % TILE);
+                    }
+            }
+        }
+        put(L.data(), L.size() * 16);
+        break;
+    }
+    case D3M_EXPORT_LAMBDA: {
+        if (h->factored != 1) return fail(D3M_ESTATE, "multiplier export needs an FP64 solve");
+        int nrhs = (int)index;
+        if (nrhs < 1 || nrhs > h->vec_nrhs[0]) return fail(D3M_EINVAL, "index must be the nrhs of the last solve");
+        const Plan &pl = h->pl;
+        std::vector<double2> xk((size_t)pl.v_tiles_k * 64 * nrhs);
+        if (hipMemcpy(xk.data(), h->vec[0][V_KX].p, xk.size() * 16, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(D3M_EHIP, "copy of the multipliers failed");
+        for (int c = 0; c < nrhs; ++c)
+            for (i64 l = 0; l < dc.n_lm; ++l) {
+                i64 R = pl.lm_vrow[l];
+                put(&xk[(size_t)(R / 64) * 64 * nrhs + (size_t)c * 64 + R % 64], 16);
+            }
+        break;
+    }
+    default: return fail(D3M_EINVAL, "unknown export selector");
+    }
+    if (buf) {
+        if (bytes < (int64_t)out.size()) return fail(D3M_EINVAL, "export buffer too small");
+        std::memcpy(buf, out.data(), out.size());
+    }
+    return (int64_t)out.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// Tile layouts and batched launch schedules.
+//
+// Step 1 (dense domain matrices) is carried out as a partial block LDL^T of
+// the augmented subdomain matrix M_d = [A_d D_d; D_d^T 0] (rows: interior
+// edges, interface edges, then the multipliers touching d): eliminating the
+// n_d edge rows leaves -D_d^T A_d^{-1} D_d = -K_D^(d) in the trailing block.
+// Step 2 sums those trailing blocks into -K; step 5 factors -K block by block
+// (Algorithm 1).  Solving the saddle system with these factors is steps 6-7:
+// forward over the edge rows of every M_d gives -g on the multiplier rows,
+// the -K solve gives lambda, and the backward sweep over the edge rows gives
+// E_d = A_d^{-1}(f_d - D_d lambda).
+#include <algorithm>
+#include <map>
+
+#include "plan.hpp"
+
+namespace d3m {
+
+namespace {
+inline int ceil_div(i64 a, i64 b) { return (int)((a + b - 1) / b); }
+inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total - (i64)t * TILE); }
+}  // namespace
+
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
+    const int N = dc.N;
+    const int nb = dc.nblk;
+    pl = Plan();
+
+    // ------------------------------------------------------------ layouts --
+    pl.TE.resize(N); pl.TL.resize(N); pl.T.resize(N); pl.fb.resize(N); pl.m_base.resize(N);
+    pl.tt_s1.resize(N); pl.drow_s1.resize(N);
+    i64 slot = 0, tt = 0, drow = 0;
+    int maxTE = 0;
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        pl.TE[d] = ceil_div(S.n, TILE);
+        pl.TL[d] = ceil_div(S.m, TILE);
+        pl.T[d] = pl.TE[d] + pl.TL[d];
+        pl.fb[d] = (int)(S.nI / TILE);
+        pl.m_base[d] = slot;
+        slot += tri_slot(pl.T[d], 0);
+        pl.tt_s1[d] = tt;
+        tt += pl.TE[d];
+        pl.drow_s1[d] = drow;
+        drow += (i64)pl.TE[d] * TILE;
+        maxTE = std::max(maxTE, pl.TE[d]);
+    }
+    pl.m_tiles = slot;
+
+    std::vector<int> nsz(nb);
+    for (int j = 0; j < nb; ++j) {
+        int b = bo.order[j];
+        nsz[j] = (int)(dc.blk_start[b + 1] - dc.blk_start[b]);
+    }
+    pl.kt.resize(nb); pl.kcol.resize(nb); pl.kR.resize(nb); pl.krow_off.resize(nb);
+    pl.tt_k.resize(nb); pl.drow_k.resize(nb);
+    for (int j = 0; j < nb; ++j) pl.kt[j] = ceil_div(nsz[j], TILE);
+    slot = 0;
+    for (int j = 0; j < nb; ++j) {
+        std::vector<int> &ro = pl.krow_off[j];
+        ro.clear();
+        int r = pl.kt[j];
+        ro.push_back(0);
+        for (int i : bo.strct[j]) { ro.push_back(r); r += pl.kt[i]; }
+        pl.kR[j] = r;
+        pl.kcol[j] = slot;
+        slot += (i64)r * pl.kt[j];
+        pl.tt_k[j] = tt;
+        tt += (i64)pl.kt[j] * pl.kt[j];
+        pl.drow_k[j] = drow;
+        drow += (i64)pl.kt[j] * TILE;
+    }
+    pl.k_tiles = slot;
+    pl.tt_tiles = tt;
+    pl.d_rows = drow;
+
+    auto mslot = [&](int d, int a, int b) { return pl.m_base[d] + tri_slot(a, b); };
+    auto mrows = [&](int d, int a) {
+        const Subdomain &S = dc.sub[d];
+        return a < pl.TE[d] ? tile_rows(S.n, a) : tile_rows(S.m, a - pl.TE[d]);
+    };
+    // row-tile offset of block i inside the panel of block column j
+    auto rowoff = [&](int j, int i) -> int {
+        if (i == j) return 0;
+        const auto &s = bo.strct[j];
+        auto it = std::lower_bound(s.begin(), s.end(), i);
+        if (it == s.end() || *it != i) throw Error{-1, "internal: block not in struct"};
+        return pl.krow_off[j][1 + (it - s.begin())];
+    };
+    auto kslot = [&](int j, int i, int a, int b) {  // block (i, j), tile (a, b)
+        return pl.kcol[j] + (i64)b * pl.kR[j] + rowoff(j, i) + a;
+    };
+    auto E = [](int arr, i64 slot_) { return enc(arr, slot_ * TILE_ELEMS); };
+
+    // --------------------------------------------- step 1 (subdomain) plan --
+    for (int j = 0; j < maxTE; ++j) {
+        FactorStep st;
+        st.bk0 = (i64)pl.bk.size();
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            BkTask t{};
+            t.a = t.l = E(ARR_M, mslot(d, j, j));
+            t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+            t.drow = pl.drow_s1[d] + (i64)j * TILE;
+            t.n = mrows(d, j);
+            t.ldt = 0;
+            t.status = (int)pl.bk.size();
+            pl.bk.push_back(t);
+            st.bk_maxn = std::max(st.bk_maxn, t.n);
+            pl.flops_s1 += 8.0 * t.n * (double)t.n * t.n / 6.0;
+        }
+        st.nbk = (i64)pl.bk.size() - st.bk0;
+        // panels: X = M(a, j) P L^-T for every nonzero row tile below j
+        st.pan0 = (i64)pl.gemm.size();
+        st.sc0 = (i64)pl.scale.size();
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            int w = mrows(d, j);
+            for (int a = j + 1; a < pl.T[d]; ++a) {
+                if (a >= pl.TE[d] && j < pl.fb[d]) continue;
+                pl.gemm.push_back({E(ARR_MX, mslot(d, a, j)), (int32_t)pl.pairs.size(), 1});
+                pl.pairs.push_back({E(ARR_M, mslot(d, a, j)), E(ARR_TT, pl.tt_s1[d] + j)});
+                ScaleTask s{};
+                s.x = E(ARR_MX, mslot(d, a, j));
+                s.w = E(ARR_M, mslot(d, a, j));
+                s.xprev = s.xnext = -1;
+                s.drow = pl.drow_s1[d] + (i64)j * TILE;
+                s.ncols = w;
+                pl.scale.push_back(s);
+                double pf = 8.0 * mrows(d, a) * (double)w * w / 2.0;
+                st.pan_flops += pf;
+                pl.flops_s1 += pf;
+            }
+        }
+        st.npan = (i64)pl.gemm.size() - st.pan0;
+        st.nsc = (i64)pl.scale.size() - st.sc0;
+        // trailing updates M(a, b) -= X(a, j) L-hat(b, j)^T
+        st.up0 = (i64)pl.gemm.size();
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            int w = mrows(d, j);
+            for (int b = j + 1; b < pl.T[d]; ++b)
+                for (int a = b; a < pl.T[d]; ++a) {
+                    if (a >= pl.TE[d] && j < pl.fb[d]) continue;
+                    pl.gemm.push_back({E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 1});
+                    pl.pairs.push_back({E(ARR_MX, mslot(d, a, j)), E(ARR_M, mslot(d, b, j))});
+                    int ra = mrows(d, a), rb = mrows(d, b);
+                    double f = 8.0 * w * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                    st.up_flops += f;
+                }
+        }
+        st.nup = (i64)pl.gemm.size() - st.up0;
+        pl.flops_s1 += st.up_flops;
+        pl.flops_update += st.up_flops;
+        pl.s1_steps.push_back(st);
+    }
+
+    // --------------------------------------------- step 2 (assembly) plan --
+    // -K(i, j) = sum over subdomains d holding both blocks of the trailing
+    // block of M_d at the rows of block i and the columns of block j
+    for (int j = 0; j < nb; ++j) {
+        int Q = bo.order[j];
+        std::vector<int> rows_blocks{j};
+        rows_blocks.insert(rows_blocks.end(), bo.strct[j].begin(), bo.strct[j].end());
+        for (int i : rows_blocks) {
+            int P = bo.order[i];
+            std::vector<int> common;
+            for (int dP : {dc.blk_p[P], dc.blk_q[P]})
+                for (int dQ : {dc.blk_p[Q], dc.blk_q[Q]})
+                    if (dP == dQ && std::find(common.begin(), common.end(), dP) == common.end())
+                        common.push_back(dP);
+            for (int b = 0; b < pl.kt[j]; ++b)
+                for (int a = (i == j ? b : 0); a < pl.kt[i]; ++a) {
+                    AsmTask t{};
+                    t.dst = E(ARR_K, kslot(j, i, a, b));
+                    t.nrow = tile_rows(nsz[i], a);
+                    t.ncol = tile_rows(nsz[j], b);
+                    t.ncontrib = (int)common.size();
+                    for (size_t c = 0; c < common.size(); ++c) {
+                        int d = common[c];
+                        const Subdomain &S = dc.sub[d];
+                        auto oP = std::lower_bound(S.blocks.begin(), S.blocks.end(), P) - S.blocks.begin();
+                        auto oQ = std::lower_bound(S.blocks.begin(), S.blocks.end(), Q) - S.blocks.begin();
+                        t.mbase[c] = pl.m_base[d];
+                        t.row0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oP] + (i64)a * TILE);
+                        t.col0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oQ] + (i64)b * TILE);
+                    }
+                    pl.asmb.push_back(t);
+                }
+        }
+    }
+
+    // ------------------------------------- step 5 (block LDL^T of -K) plan --
+    std::vector<std::vector<int>> by_level(bo.n_levels);
+    for (int j = 0; j < nb; ++j) by_level[bo.level[j]].push_back(j);
+    const int LDS_MAX_N = 136;
+    for (int L = 0; L < bo.n_levels; ++L) {
+        const auto &J = by_level[L];
+        FactorStep st;
+        st.bk0 = (i64)pl.bk.size();
+        for (int j : J) {
+            BkTask t{};
+            t.a = E(ARR_K, pl.kcol[j]);
+            t.l = E(ARR_KL, pl.kcol[j]);
+            t.tt = E(ARR_TT, pl.tt_k[j]);
+            t.drow = pl.drow_k[j];
+            t.n = nsz[j];
+            t.ldt = (int32_t)((i64)pl.kR[j] * TILE_ELEMS);
+            t.status = (int)pl.bk.size();
+            pl.bk.push_back(t);
+            st.bk_maxn = std::max(st.bk_maxn, t.n);
+            pl.flops_s3 += 8.0 * (double)t.n * t.n * t.n / 6.0;
+        }
+        st.nbk = (i64)pl.bk.size() - st.bk0;
+        if (st.bk_maxn > LDS_MAX_N)
+            pl.bk_scratch_elems = std::max<i64>(pl.bk_scratch_elems,
+                                                st.nbk * ((i64)st.bk_maxn * (st.bk_maxn + 1) / 2));
+        st.pan0 = (i64)pl.gemm.size();
+        st.sc0 = (i64)pl.scale.size();
+        for (int j : J) {
+            int tj = pl.kt[j];
+            for (int i : bo.strct[j])
+                for (int a = 0; a < pl.kt[i]; ++a)
+                    for (int b = 0; b < tj; ++b) {
+                        pl.gemm.push_back({E(ARR_KX, kslot(j, i, a, b)), (int32_t)pl.pairs.size(), tj});
+                        for (int c = 0; c < tj; ++c)
+                            pl.pairs.push_back({E(ARR_K, kslot(j, i, a, c)),
+                                                E(ARR_TT, pl.tt_k[j] + (i64)c * tj + b)});
+                        ScaleTask s{};
+                        s.x = E(ARR_KX, kslot(j, i, a, b));
+                        s.w = E(ARR_KL, kslot(j, i, a, b));
+                        s.xprev = b > 0 ? E(ARR_KX, kslot(j, i, a, b - 1)) : -1;
+                        s.xnext = b + 1 < tj ? E(ARR_KX, kslot(j, i, a, b + 1)) : -1;
+                        s.drow = pl.drow_k[j] + (i64)b * TILE;
+                        s.ncols = tile_rows(nsz[j], b);
+                        pl.scale.push_back(s);
+                    }
+            double pf = 0.0;
+            for (int i : bo.strct[j]) pf += 8.0 * nsz[i] * (double)nsz[j] * nsz[j] / 2.0;
+            st.pan_flops += pf;
+            pl.flops_s3 += pf;
+        }
+        st.npan = (i64)pl.gemm.size() - st.pan0;
+        st.nsc = (i64)pl.scale.size() - st.sc0;
+        // updates grouped by target block so that every target tile is
+        // written by exactly one work-group (deterministic, atomic-free)
+        std::map<std::pair<int, int>, std::vector<int>> targets;
+        for (int j : J)
+            for (size_t x = 0; x < bo.strct[j].size(); ++x)
+                for (size_t y = 0; y <= x; ++y)
+                    targets[{bo.strct[j][x], bo.strct[j][y]}].push_back(j);
+        st.up0 = (i64)pl.gemm.size();
+        for (auto &kv : targets) {
+            int i = kv.first.first, k = kv.first.second;
+            for (int b = 0; b < pl.kt[k]; ++b)
+                for (int a = (i == k ? b : 0); a < pl.kt[i]; ++a) {
+                    GemmTask g{E(ARR_K, kslot(k, i, a, b)), (int32_t)pl.pairs.size(), 0};
+                    int ra = tile_rows(nsz[i], a), rb = tile_rows(nsz[k], b);
+                    for (int j : kv.second)
+                        for (int c = 0; c < pl.kt[j]; ++c) {
+                            pl.pairs.push_back({E(ARR_KX, kslot(j, i, a, c)), E(ARR_KL, kslot(j, k, b, c))});
+                            ++g.np;
+                            int w = tile_rows(nsz[j], c);
+                            st.up_flops += 8.0 * w * ((i == k && a == b) ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                        }
+                    pl.gemm.push_back(g);
+                }
+        }
+        st.nup = (i64)pl.gemm.size() - st.up0;
+        pl.flops_s3 += st.up_flops;
+        pl.flops_update += st.up_flops;
+        pl.k_steps.push_back(st);
+    }
+    pl.n_status = (int)pl.bk.size();
+
+    // ------------------------------------------------ scatter of A_d, D_d --
+    pl.coo_off.clear();
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (size_t x = 0; x < S.a_row.size(); ++x) {
+            i64 r = S.a_row[x], c = S.a_col[x];
+            pl.coo_off.push_back(mslot(d, (int)(r / TILE), (int)(c / TILE)) * TILE_ELEMS + (c % TILE) * TILE + r % TILE);
+        }
+    }
+    pl.n_coo_a = (i64)pl.coo_off.size();
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (size_t ob = 0; ob < S.blocks.size(); ++ob) {
+            int P = S.blocks[ob];
+            for (i64 l = dc.blk_start[P]; l < dc.blk_start[P + 1]; ++l) {
+                i64 r = (i64)pl.TE[d] * TILE + S.block_off[ob] + (l - dc.blk_start[P]);
+                i64 c = S.row_of(dc.lm_e[l]);
+                pl.coo_off.push_back(mslot(d, (int)(r / TILE), (int)(c / TILE)) * TILE_ELEMS + (c % TILE) * TILE + r % TILE);
+            }
+        }
+    }
+
+    // ------------------------------------------------------ solve plan ----
+    pl.vs1.resize(N);
+    i64 v = 0;
+    for (int d = 0; d < N; ++d) { pl.vs1[d] = v; v += pl.T[d]; }
+    pl.v_tiles_s1 = v;
+    pl.vk.resize(nb);
+    v = 0;
+    for (int j = 0; j < nb; ++j) { pl.vk[j] = v; v += pl.kt[j]; }
+    pl.v_tiles_k = v;
+    auto V = [](int arr, i64 tile) { return enc(arr, tile); };
+
+    pl.split_map.assign(pl.v_tiles_s1 * TILE, -1);
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (i64 r = 0; r < S.n; ++r) {
+            i64 e = S.edges[r];
+            if (dc.owner[e] == d) pl.split_map[pl.vs1[d] * TILE + r] = e;
+        }
+    }
+    pl.collect_map.assign(dc.owner.size(), -1);
+    for (size_t e = 0; e < dc.owner.size(); ++e) {
+        int d = dc.owner[e];
+        pl.collect_map[e] = pl.vs1[d] * TILE + dc.sub[d].row_of((i64)e);
+    }
+    // multiplier rows: K vector row <-> the two subdomain copies
+    std::vector<i64> &kvrow_of_lm = pl.lm_vrow;
+    kvrow_of_lm.assign(dc.n_lm, -1);
+    for (int j = 0; j < nb; ++j) {
+        int P = bo.order[j];
+        for (i64 l = dc.blk_start[P]; l < dc.blk_start[P + 1]; ++l)
+            kvrow_of_lm[l] = pl.vk[j] * TILE + (l - dc.blk_start[P]);
+    }
+    std::vector<int64_t> &hmap = pl.h_map;
+    hmap.assign(pl.v_tiles_k * TILE * 2, -1);
+    std::vector<int64_t> &lmap = pl.lam_map;
+    lmap.assign(pl.v_tiles_s1 * TILE, -1);
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (size_t ob = 0; ob < S.blocks.size(); ++ob) {
+            int P = S.blocks[ob];
+            for (i64 l = dc.blk_start[P]; l < dc.blk_start[P + 1]; ++l) {
+                i64 srow = pl.vs1[d] * TILE + (i64)pl.TE[d] * TILE + S.block_off[ob] + (l - dc.blk_start[P]);
+                i64 kr = kvrow_of_lm[l];
+                int slotc = hmap[2 * kr] < 0 ? 0 : 1;
+                hmap[2 * kr + slotc] = srow;
+                lmap[srow] = kr;
+            }
+        }
+    }
+
+    // S1 forward
+    for (int j = 0; j < maxTE; ++j) {
+        SolveStep st;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            VDiagTask t{};
+            t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+            t.x = V(V_X, pl.vs1[d] + j); t.y = V(V_Y, pl.vs1[d] + j); t.v = V(V_V, pl.vs1[d] + j);
+            t.acc = -1;
+            t.drow = pl.drow_s1[d] + (i64)j * TILE;
+            t.t = 1; t.n = mrows(d, j);
+            pl.vdiag.push_back(t);
+        }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 0;
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            for (int a = j + 1; a < pl.T[d]; ++a) {
+                if (a >= pl.TE[d] && j < pl.fb[d]) continue;
+                pl.vupd.push_back({V(V_X, pl.vs1[d] + a), (int32_t)pl.vpairs.size(), 1});
+                pl.vpairs.push_back({E(ARR_M, mslot(d, a, j)), V(V_Y, pl.vs1[d] + j)});
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.s1_fwd.push_back(st);
+    }
+    // K forward / backward
+    for (int L = 0; L < bo.n_levels; ++L) {
+        SolveStep st;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int j : by_level[L]) {
+            VDiagTask t{};
+            t.tt = E(ARR_TT, pl.tt_k[j]);
+            t.x = V(V_KX, pl.vk[j]); t.y = V(V_KY, pl.vk[j]); t.v = V(V_KV, pl.vk[j]);
+            t.acc = -1;
+            t.drow = pl.drow_k[j];
+            t.t = pl.kt[j]; t.n = nsz[j];
+            pl.vdiag.push_back(t);
+        }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        std::map<int, std::vector<int>> targets;
+        for (int j : by_level[L])
+            for (int i : bo.strct[j]) targets[i].push_back(j);
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 0;
+        for (auto &kv : targets) {
+            int i = kv.first;
+            for (int a = 0; a < pl.kt[i]; ++a) {
+                VUpdTask u{V(V_KX, pl.vk[i] + a), (int32_t)pl.vpairs.size(), 0};
+                for (int j : kv.second)
+                    for (int c = 0; c < pl.kt[j]; ++c) {
+                        pl.vpairs.push_back({E(ARR_KL, kslot(j, i, a, c)), V(V_KY, pl.vk[j] + c)});
+                        ++u.np;
+                    }
+                pl.vupd.push_back(u);
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.k_fwd.push_back(st);
+    }
+    for (int L = bo.n_levels - 1; L >= 0; --L) {
+        SolveStep st;
+        st.up_first = true;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 1;
+        for (int j : by_level[L])
+            for (int b = 0; b < pl.kt[j]; ++b) {
+                VUpdTask u{V(V_KACC, pl.vk[j] + b), (int32_t)pl.vpairs.size(), 0};
+                for (int i : bo.strct[j])
+                    for (int a = 0; a < pl.kt[i]; ++a) {
+                        pl.vpairs.push_back({E(ARR_KL, kslot(j, i, a, b)), V(V_KX, pl.vk[i] + a)});
+                        ++u.np;
+                    }
+                pl.vupd.push_back(u);
+            }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int j : by_level[L]) {
+            VDiagTask t{};
+            t.tt = E(ARR_TT, pl.tt_k[j]);
+            t.x = V(V_KX, pl.vk[j]); t.y = -1; t.v = V(V_KV, pl.vk[j]);
+            t.acc = V(V_KACC, pl.vk[j]);
+            t.drow = pl.drow_k[j];
+            t.t = pl.kt[j]; t.n = nsz[j];
+            pl.vdiag.push_back(t);
+        }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        pl.k_bwd.push_back(st);
+    }
+    // S1 backward: first the multiplier rows' contribution, then tile columns
+    {
+        SolveStep st;
+        st.ndg = 0;
+        st.up_first = true;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 1;
+        for (int d = 0; d < N; ++d)
+            for (int c = 0; c < pl.TE[d]; ++c) {
+                VUpdTask u{V(V_ACC, pl.vs1[d] + c), (int32_t)pl.vpairs.size(), 0};
+                if (c >= pl.fb[d])
+                    for (int a = pl.TE[d]; a < pl.T[d]; ++a) {
+                        pl.vpairs.push_back({E(ARR_M, mslot(d, a, c)), V(V_X, pl.vs1[d] + a)});
+                        ++u.np;
+                    }
+                pl.vupd.push_back(u);
+            }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.s1_bwd.push_back(st);
+    }
+    for (int j = maxTE - 1; j >= 0; --j) {
+        SolveStep st;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            VDiagTask t{};
+            t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+            t.x = V(V_X, pl.vs1[d] + j); t.y = -1; t.v = V(V_V, pl.vs1[d] + j);
+            t.acc = V(V_ACC, pl.vs1[d] + j);
+            t.drow = pl.drow_s1[d] + (i64)j * TILE;
+            t.t = 1; t.n = mrows(d, j);
+            pl.vdiag.push_back(t);
+        }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 2;
+        for (int d = 0; d < N; ++d) {
+            if (j >= pl.TE[d]) continue;
+            for (int c = 0; c < j; ++c) {
+                pl.vupd.push_back({V(V_ACC, pl.vs1[d] + c), (int32_t)pl.vpairs.size(), 1});
+                pl.vpairs.push_back({E(ARR_M, mslot(d, j, c)), V(V_X, pl.vs1[d] + j)});
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.s1_bwd.push_back(st);
+    }
+
+    // ------------------------------------------------ algorithmic counts --
+    i64 ent = 0;
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (i64 c = 0; c < S.n; ++c) ent += (S.n - c - 1) + (c >= S.nI ? S.m : 0);
+    }
+    for (int j = 0; j < nb; ++j) {
+        ent += (i64)nsz[j] * (nsz[j] - 1) / 2;
+        for (int i : bo.strct[j]) ent += (i64)nsz[i] * nsz[j];
+    }
+    pl.factor_entries = ent;
+    pl.solve_bytes = 2.0 * 16.0 * (double)ent;
+}
+
+}  // namespace d3m

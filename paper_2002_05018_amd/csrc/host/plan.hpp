@@ -1,0 +1,80 @@
+// Tile layouts and launch schedules of the factor and solve phases.
+#pragma once
+
+#include <vector>
+
+#include "../tasks.hpp"
+#include "problem.hpp"
+
+namespace d3m {
+
+// One batched step of the factorisation: a Bunch-Kaufman launch over the
+// diagonal blocks of the step, a panel GEMM launch (X = M P L^-T), a scaling
+// launch (L-hat = X D^-1) and a trailing-update GEMM launch.
+struct FactorStep {
+    i64 bk0 = 0, nbk = 0;
+    int bk_maxn = 0;
+    i64 pan0 = 0, npan = 0;
+    i64 sc0 = 0, nsc = 0;
+    i64 up0 = 0, nup = 0;
+    double up_flops = 0.0;   // algorithmic flops of the update GEMMs
+    double pan_flops = 0.0;  // algorithmic flops of the panels (triangular solves)
+};
+
+// One sweep step of the solve: a diagonal launch and an update launch.
+struct SolveStep {
+    i64 dg0 = 0, ndg = 0;
+    i64 up0 = 0, nup = 0;
+    int up_mode = 0;  // 0: out -= sum L y   1: out = sum L^T x   2: out += sum L^T x
+    bool up_first = false;  // run the update launch before the diagonal launch
+};
+
+struct Plan {
+    // ---- subdomain matrices M_d = [A_d D_d; D_d^T 0] --------------------
+    std::vector<int> TE, TL, T, fb;    // E tiles, LM tiles, total, first tile column holding interface rows
+    std::vector<i64> m_base;           // tile slot of tile (0,0) of each subdomain in ARR_M
+    i64 m_tiles = 0;
+    // ---- LM Schur complement (-K), elimination-position order -----------
+    std::vector<int> kt;               // tiles per block
+    std::vector<i64> kcol;             // slot of the panel's tile (0,0) for each block column
+    std::vector<int> kR;               // row tiles of each block-column panel
+    std::vector<std::vector<int>> krow_off;  // per block column j: row-tile offset of block struct(j)[i]
+    i64 k_tiles = 0;
+    // ---- TT tiles and D rows ---------------------------------------------
+    std::vector<i64> tt_s1, tt_k;      // TT tile slot per subdomain (then +j) / per block
+    i64 tt_tiles = 0;
+    std::vector<i64> drow_s1, drow_k;  // first D row per subdomain / per block
+    i64 d_rows = 0;
+    int n_status = 0;
+    // ---- factor schedule ------------------------------------------------
+    std::vector<BkTask> bk;
+    std::vector<GemmTask> gemm;
+    std::vector<GemmPair> pairs;
+    std::vector<ScaleTask> scale;
+    std::vector<AsmTask> asmb;
+    std::vector<FactorStep> s1_steps, k_steps;
+    std::vector<int64_t> coo_off;      // ARR_M element of each A_d / D_d entry
+    i64 n_coo_a = 0;                   // leading entries that are A_d values
+    i64 bk_scratch_elems = 0;          // per-launch global scratch for big blocks
+    // ---- solve schedule ---------------------------------------------------
+    std::vector<i64> vs1;              // first vector tile of each subdomain
+    std::vector<i64> vk;               // first vector tile of each block (position)
+    i64 v_tiles_s1 = 0, v_tiles_k = 0;
+    std::vector<int64_t> split_map;    // per S1 vector row: global edge if owner, else -1
+    std::vector<int64_t> collect_map;  // per global edge: S1 vector row of its owner copy
+    std::vector<VDiagTask> vdiag;
+    std::vector<VUpdTask> vupd;
+    std::vector<VUpdPair> vpairs;
+    std::vector<SolveStep> s1_fwd, k_fwd, k_bwd, s1_bwd;
+    std::vector<int64_t> h_map;        // per K vector row: the two subdomain vector rows (-1: padding)
+    std::vector<int64_t> lam_map;      // per S1 vector row: K vector row of a multiplier row, else -1
+    std::vector<int64_t> lm_vrow;      // per global multiplier: its K vector row
+    // ---- algorithmic counts -----------------------------------------------
+    double flops_s1 = 0.0, flops_s3 = 0.0, flops_update = 0.0;
+    double solve_bytes = 0.0;          // complex128 factor bytes read per solve
+    i64 factor_entries = 0;
+};
+
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo);
+
+}  // namespace d3m

@@ -1,0 +1,42 @@
+// Device helpers shared by the factor and solve kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../tasks.hpp"
+
+namespace d3m {
+
+template <typename T> struct C2T;
+template <> struct C2T<double> { using type = double2; };
+template <> struct C2T<float> { using type = float2; };
+
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+template <typename T2> __device__ __forceinline__ T2 from_d2(double2 v);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a - b*c
+__device__ __forceinline__ double2 cfms(double2 a, double2 b, double2 c) {
+    return make_double2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
+}
+// 1/z from the definition conj(z)/|z|^2 (scaled to avoid overflow)
+__device__ __forceinline__ double2 crecip(double2 z) {
+    double s = fmax(fabs(z.x), fabs(z.y));
+    double xr = z.x / s, xi = z.y / s;
+    double den = (xr * xr + xi * xi) * s;
+    return make_double2(xr / den, -xi / den);
+}
+__device__ __forceinline__ double cabs1(double2 z) { return fabs(z.x) + fabs(z.y); }
+
+template <typename T2> __device__ __forceinline__ T2 *enc_ptr(const Bases &b, int64_t e) {
+    return reinterpret_cast<T2 *>(b.p[e >> ENC_SHIFT]) + (e & ENC_MASK);
+}
+
+}  // namespace d3m

@@ -1,0 +1,64 @@
+// Host-side launchers of the HIP kernels (declarations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../tasks.hpp"
+
+namespace d3m {
+
+// Pivot data of every diagonal block, FP64 for both precisions, indexed by
+// the "D row" of the block (see the planner).
+struct DArrays {
+    double2 *d, *doff;      // D diagonal and 2x2 off-diagonal
+    double2 *dinv, *dinvoff;
+    int *piv;               // 0: 1x1, 1: first row of a 2x2, -1: second row
+    int *perm;              // block-local permutation
+};
+
+struct VBases {
+    void *p[VARR_COUNT];
+};
+
+template <typename T> hipError_t launch_fill_zero(void *p, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_coo_scatter(void *M, const int64_t *off, const double2 *val, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &b, const DArrays &D, int *status,
+                     double2 *scratch, hipStream_t s);
+size_t bk_lds_bytes(int n, int nthr, bool lds);
+template <typename T>
+hipError_t launch_gemm(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs, const Bases &b, int mode,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_scale(const ScaleTask *tasks, int64_t ntask, const Bases &b, const DArrays &D, hipStream_t s);
+template <typename T> hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipStream_t s);
+
+// solve sweeps
+template <typename T>
+hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t nrows, int nrhs, int64_t ne,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, bool bwd, const Bases &b, const VBases &vb,
+                        const DArrays &D, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pairs, int mode, const Bases &b,
+                       const VBases &vb, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_vscatter_lam(void *X, const void *XK, const int64_t *lmap, int64_t nrows_s1, int nrhs,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64_t ne, int nrhs, bool accumulate,
+                           hipStream_t s);
+
+// refinement and adjoint
+hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
+                           const double2 *val, int64_t ne, int nrhs, hipStream_t s);
+hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s);
+hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s);
+hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E, const int64_t *tet_edges,
+                               const double *mass, double k2, int64_t nt, int64_t ne, int nrhs, hipStream_t s);
+
+}  // namespace d3m

@@ -1,0 +1,331 @@
+// Solve-phase kernels (recipe steps 6-7 of Section II) and the FP64
+// refinement / adjoint helpers.  Vector tiles hold 64 rows x nrhs columns,
+// column-major (one right-hand side after another), so one 64 x 64 factor
+// tile is applied to every right-hand side while it sits in LDS.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace d3m {
+
+template <typename T2>
+__device__ __forceinline__ T2 *vptr(const VBases &vb, int64_t e, int nrhs) {
+    return reinterpret_cast<T2 *>(vb.p[e >> ENC_SHIFT]) + (e & ENC_MASK) * 64 * (int64_t)nrhs;
+}
+// element of vector row R (tile R/64, row R%64), column c
+__device__ __forceinline__ int64_t vrow_elem(int64_t R, int c, int nrhs) {
+    return (R >> 6) * 64 * (int64_t)nrhs + (int64_t)c * 64 + (R & 63);
+}
+
+// X[row] = f[c][e] for rows whose edge is owned by this subdomain, else 0
+template <typename T2>
+__global__ void vsplit_kernel(T2 *X, const double2 *f, const int64_t *map, int64_t nrows, int nrhs, int64_t ne) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * nrhs) return;
+    int64_t tile = idx / (64 * nrhs);
+    int rem = (int)(idx - tile * 64 * nrhs);
+    int c = rem >> 6, r = rem & 63;
+    int64_t e = map[tile * 64 + r];
+    X[idx] = e >= 0 ? from_d2<T2>(f[(int64_t)c * ne + e]) : T2{0, 0};
+}
+
+// Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y.
+// Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
+template <typename T2, bool BWD>
+__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
+    const VDiagTask tk = tasks[blockIdx.x];
+    const int t = tk.t;
+    const T2 *TT = enc_ptr<T2>(b, tk.tt);
+    const int64_t vt = 64 * (int64_t)nrhs;
+    if (!BWD) {
+        const T2 *x = vptr<T2>(vb, tk.x, nrhs);
+        T2 *y = vptr<T2>(vb, tk.y, nrhs);
+        T2 *v = vptr<T2>(vb, tk.v, nrhs);
+        for (int bt = 0; bt < t; ++bt)
+            for (int e = threadIdx.x; e < vt; e += blockDim.x) {
+                const int r = e & 63, c = e >> 6;
+                double2 acc = make_double2(0, 0);
+                for (int ct = 0; ct < t; ++ct) {
+                    const T2 *tile = TT + ((int64_t)ct * t + bt) * TILE_ELEMS_D;
+                    const T2 *xs = x + ct * vt + c * 64;
+                    for (int q = 0; q < 64; ++q) acc = cadd(acc, cmul(to_d2(tile[q * 64 + r]), to_d2(xs[q])));
+                }
+                y[bt * vt + e] = from_d2<T2>(acc);
+            }
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < t * vt; e += blockDim.x) {
+            const int bt = (int)(e / vt);
+            const int rem = (int)(e - bt * vt);
+            const int r = rem & 63, c = rem >> 6;
+            const int row = bt * 64 + r;
+            const int64_t dr = tk.drow + row;
+            double2 val = make_double2(0, 0);
+            if (row < tk.n) {
+                val = cmul(D.dinv[dr], to_d2(y[e]));
+                const int pv = D.piv[dr];
+                if (pv != 0) {
+                    const int pr = row + pv;
+                    val = cadd(val, cmul(D.dinvoff[dr], to_d2(y[(pr >> 6) * vt + c * 64 + (pr & 63)])));
+                }
+            }
+            v[e] = from_d2<T2>(val);
+        }
+    } else {
+        T2 *x = vptr<T2>(vb, tk.x, nrhs);
+        const T2 *v = vptr<T2>(vb, tk.v, nrhs);
+        const T2 *acc = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
+        for (int ct = 0; ct < t; ++ct)
+            for (int e = threadIdx.x; e < vt; e += blockDim.x) {
+                const int r = e & 63, c = e >> 6;
+                double2 s = make_double2(0, 0);
+                for (int bt = 0; bt < t; ++bt) {
+                    const T2 *tile = TT + ((int64_t)ct * t + bt) * TILE_ELEMS_D;
+                    const T2 *vs = v + bt * vt + c * 64;
+                    const T2 *as = acc ? acc + bt * vt + c * 64 : nullptr;
+                    for (int q = 0; q < 64; ++q) {
+                        double2 w = to_d2(vs[q]);
+                        if (as) w = csub(w, to_d2(as[q]));
+                        s = cadd(s, cmul(to_d2(tile[r * 64 + q]), w));
+                    }
+                }
+                x[ct * vt + e] = from_d2<T2>(s);
+            }
+    }
+}
+
+// out (-=|=|+=) sum_p op(L_p) src_p with op = identity (mode 0) or
+// transpose (modes 1, 2); the factor tile is staged through LDS.
+template <typename T2, int MODE>
+__global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const VUpdPair *pairs, Bases b, VBases vb,
+                                                   int nrhs) {
+    __shared__ T2 Ls[64 * 65];
+    const VUpdTask tk = tasks[blockIdx.x];
+    const int c0 = blockIdx.y * 32;
+    const int ncol = min(32, nrhs - c0);
+    T2 *out = vptr<T2>(vb, tk.out, nrhs);
+    double2 acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = make_double2(0, 0);
+    for (int p = 0; p < tk.np; ++p) {
+        const VUpdPair pr = pairs[tk.p0 + p];
+        const T2 *L = enc_ptr<T2>(b, pr.l);
+        const T2 *src = vptr<T2>(vb, pr.src, nrhs);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 4096; e += 256) Ls[(e >> 6) * 65 + (e & 63)] = L[e];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            if (c < ncol) {
+                const T2 *s = src + (int64_t)(c0 + c) * 64;
+                double2 a = acc[i];
+                if (MODE == 0) {
+                    for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[q * 65 + r]), to_d2(s[q])));
+                } else {
+                    for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[r * 65 + q]), to_d2(s[q])));
+                }
+                acc[i] = a;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        const int c = e >> 6;
+        if (c < ncol) {
+            T2 *o = out + (int64_t)c0 * 64 + e;
+            if (MODE == 0) *o = from_d2<T2>(csub(to_d2(*o), acc[i]));
+            else if (MODE == 1) *o = from_d2<T2>(acc[i]);
+            else *o = from_d2<T2>(cadd(to_d2(*o), acc[i]));
+        }
+    }
+}
+
+// XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
+template <typename T2>
+__global__ void vgather_h_kernel(T2 *XK, const T2 *X, const int64_t *hmap, int64_t nrows, int nrhs) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * nrhs) return;
+    int64_t tile = idx / (64 * nrhs);
+    int rem = (int)(idx - tile * 64 * nrhs);
+    int c = rem >> 6, r = rem & 63;
+    int64_t R = tile * 64 + r;
+    double2 s = make_double2(0, 0);
+    int64_t a = hmap[2 * R], bb = hmap[2 * R + 1];
+    if (a >= 0) s = cadd(s, to_d2(X[vrow_elem(a, c, nrhs)]));
+    if (bb >= 0) s = cadd(s, to_d2(X[vrow_elem(bb, c, nrhs)]));
+    XK[idx] = from_d2<T2>(s);
+}
+
+// X[R] = XK[lmap(R)] on the multiplier rows of every subdomain
+template <typename T2>
+__global__ void vscatter_lam_kernel(T2 *X, const T2 *XK, const int64_t *lmap, int64_t nrows, int nrhs) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * nrhs) return;
+    int64_t tile = idx / (64 * nrhs);
+    int rem = (int)(idx - tile * 64 * nrhs);
+    int c = rem >> 6, r = rem & 63;
+    int64_t src = lmap[tile * 64 + r];
+    if (src >= 0) X[idx] = XK[vrow_elem(src, c, nrhs)];
+}
+
+// E[c][e] (=|+=) X[owner row of e]
+template <typename T2, bool ACC>
+__global__ void vcollect_kernel(double2 *E, const T2 *X, const int64_t *cmap, int64_t ne, int nrhs) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * nrhs) return;
+    int c = (int)(idx / ne);
+    int64_t e = idx - (int64_t)c * ne;
+    double2 v = to_d2(X[vrow_elem(cmap[e], c, nrhs)]);
+    E[idx] = ACC ? cadd(E[idx], v) : v;
+}
+
+// r = f - S E (CSR of the global FEM matrix, FP64)
+__global__ void residual_kernel(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr,
+                                const int32_t *col, const double2 *val, int64_t ne, int nrhs) {
+    int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= ne) return;
+    for (int c = 0; c < nrhs; ++c) {
+        double2 s = f[(int64_t)c * ne + row];
+        const double2 *Ec = E + (int64_t)c * ne;
+        for (int64_t k = rowptr[row]; k < rowptr[row + 1]; ++k) s = cfms(s, val[k], Ec[col[k]]);
+        r[(int64_t)c * ne + row] = s;
+    }
+}
+
+// out[c] = max_e |v[c][e]| (infinity norm with |z| = modulus), as the bit
+// pattern of a non-negative double (monotone under unsigned comparison)
+__global__ void rownorm_max_kernel(unsigned long long *out, const double2 *v, int64_t ne, int nrhs) {
+    int c = blockIdx.y;
+    double m = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 z = v[(int64_t)c * ne + e];
+        m = fmax(m, sqrt(z.x * z.x + z.y * z.y));
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(&out[c], (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void conj_kernel(double2 *out, const double2 *in, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_double2(in[i].x, -in[i].y);
+}
+
+// grad[t] = k^2 Re sum_c w_t^T M_t E_t (M_t: unit-eps_r element mass, 6x6)
+__global__ void adjoint_grad_kernel(double *grad, const double2 *w, const double2 *E, const int64_t *tet_edges,
+                                    const double *mass, double k2, int64_t nt, int64_t ne, int nrhs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int64_t ed[6];
+    for (int a = 0; a < 6; ++a) ed[a] = tet_edges[6 * t + a];
+    const double *M = mass + 36 * t;
+    double s = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        double2 wl[6], el[6];
+        for (int a = 0; a < 6; ++a) { wl[a] = w[(int64_t)c * ne + ed[a]]; el[a] = E[(int64_t)c * ne + ed[a]]; }
+        for (int a = 0; a < 6; ++a) {
+            double2 me = make_double2(0, 0);
+            for (int bb = 0; bb < 6; ++bb) me = make_double2(me.x + M[6 * a + bb] * el[bb].x, me.y + M[6 * a + bb] * el[bb].y);
+            s += wl[a].x * me.x - wl[a].y * me.y;
+        }
+    }
+    grad[t] = k2 * s;
+}
+
+// ------------------------------------------------------------ launchers --
+namespace {
+inline dim3 g1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1)); }
+}  // namespace
+
+template <typename T>
+hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t nrows, int nrhs, int64_t ne,
+                         hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    hipLaunchKernelGGL(vsplit_kernel<T2>, g1(nrows * nrhs), dim3(256), 0, s, (T2 *)X, f, map, nrows, nrhs, ne);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, bool bwd, const Bases &b, const VBases &vb,
+                        const DArrays &D, int nrhs, hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    if (ntask <= 0) return hipSuccess;
+    if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    else hipLaunchKernelGGL((vdiag_kernel<T2, false>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pairs, int mode, const Bases &b,
+                       const VBases &vb, int nrhs, hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    if (ntask <= 0) return hipSuccess;
+    dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
+    if (mode == 0) hipLaunchKernelGGL((vupd_kernel<T2, 0>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
+    else if (mode == 1) hipLaunchKernelGGL((vupd_kernel<T2, 1>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
+    else hipLaunchKernelGGL((vupd_kernel<T2, 2>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    if (nrows_k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vgather_h_kernel<T2>, g1(nrows_k * nrhs), dim3(256), 0, s, (T2 *)XK, (const T2 *)X, hmap,
+                       nrows_k, nrhs);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vscatter_lam(void *X, const void *XK, const int64_t *lmap, int64_t nrows_s1, int nrhs,
+                               hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    hipLaunchKernelGGL(vscatter_lam_kernel<T2>, g1(nrows_s1 * nrhs), dim3(256), 0, s, (T2 *)X, (const T2 *)XK, lmap,
+                       nrows_s1, nrhs);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64_t ne, int nrhs, bool accumulate,
+                           hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    if (accumulate)
+        hipLaunchKernelGGL((vcollect_kernel<T2, true>), g1(ne * nrhs), dim3(256), 0, s, E, (const T2 *)X, cmap, ne, nrhs);
+    else
+        hipLaunchKernelGGL((vcollect_kernel<T2, false>), g1(ne * nrhs), dim3(256), 0, s, E, (const T2 *)X, cmap, ne, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
+                           const double2 *val, int64_t ne, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, g1(ne), dim3(256), 0, s, r, f, E, rowptr, col, val, ne, nrhs);
+    return hipGetLastError();
+}
+hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s) {
+    int64_t blocks = (ne + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(rownorm_max_kernel, dim3((unsigned)blocks, (unsigned)nrhs), dim3(256), 0, s, out, v, ne, nrhs);
+    return hipGetLastError();
+}
+hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(conj_kernel, g1(n), dim3(256), 0, s, out, in, n);
+    return hipGetLastError();
+}
+hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E, const int64_t *tet_edges,
+                               const double *mass, double k2, int64_t nt, int64_t ne, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(adjoint_grad_kernel, g1(nt), dim3(256), 0, s, grad, w, E, tet_edges, mass, k2, nt, ne, nrhs);
+    return hipGetLastError();
+}
+
+#define D3M_INST(T)                                                                                               \
+    template hipError_t launch_vsplit<T>(void *, const double2 *, const int64_t *, int64_t, int, int64_t,          \
+                                         hipStream_t);                                                            \
+    template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, bool, const Bases &, const VBases &,           \
+                                        const DArrays &, int, hipStream_t);                                       \
+    template hipError_t launch_vupd<T>(const VUpdTask *, int64_t, const VUpdPair *, int, const Bases &,            \
+                                       const VBases &, int, hipStream_t);                                         \
+    template hipError_t launch_vgather_h<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);     \
+    template hipError_t launch_vscatter_lam<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);  \
+    template hipError_t launch_vcollect<T>(double2 *, const void *, const int64_t *, int64_t, int, bool,           \
+                                           hipStream_t);
+D3M_INST(double)
+D3M_INST(float)
+#undef D3M_INST
+
+}  // namespace d3m
