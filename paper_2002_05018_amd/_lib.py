@@ -164,7 +164,8 @@ class Solver:
     def factor(self, precision=FP64, stream=None):
         if isinstance(precision, str):
             precision = {"fp64": FP64, "fp32_ir": FP32_IR}[precision]
-        _check(_lib.d3m_factor(self._handle, int(precision), _stream_handle(stream)))
+        hs = C.c_void_p(0) if self.host_only else _stream_handle(stream)
+        _check(_lib.d3m_factor(self._handle, int(precision), hs))
 
     def solve(self, rhs, out=None, stream=None, with_info=False):
         """E = S^{-1} f for rhs [nrhs, n_edges] complex128 (torch tensor on the

@@ -17,6 +17,7 @@ class D3MSolve(torch.autograd.Function):
         solver.factor(precision)
         E = solver.solve(rhs.detach())
         ctx.solver = solver
+        ctx.eps_device = eps_r.device
         ctx.save_for_backward(E)
         ctx.rhs_requires_grad = rhs.requires_grad
         return E
@@ -27,4 +28,4 @@ class D3MSolve(torch.autograd.Function):
         solver = ctx.solver
         grad_eps, w = solver.adjoint(grad_E.contiguous(), E, want_w=True)
         grad_rhs = torch.conj(w) if ctx.rhs_requires_grad else None
-        return grad_eps.to(torch.float64), None, grad_rhs, None
+        return grad_eps.to(device=ctx.eps_device, dtype=torch.float64), None, grad_rhs, None
