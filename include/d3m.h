@@ -79,9 +79,13 @@ typedef struct {
                              d3m_kernel_stats); adds a little launch overhead */
     double ir_tol;        /* FP32_IR: stop when max over right-hand sides of
                              ||f - S E||_inf / ||f||_inf <= ir_tol (1e-10)   */
-    int32_t use_graph;    /* 1: replay each phase from a captured hipGraph  */
+    int32_t use_graph;    /* reserved (0)                                     */
     int32_t device;       /* HIP device ordinal (default 0)                   */
-    int32_t reserved[8];
+    int32_t pivot_scope;  /* Bunch-Kaufman pivot search of step 5 restricted
+                             to: 0 (default) consecutive pieces of at most 64
+                             rows of each block of K; 1 whole blocks, as in
+                             Algorithm 1 (slower: the search is sequential)  */
+    int32_t reserved[7];
 } d3m_options;
 
 typedef struct {
@@ -101,7 +105,9 @@ typedef struct {
     double solve_bytes;       /* algorithmic factor bytes read by one solve
                                  (complex128), excluding vector traffic      */
     int32_t factored;         /* 0 none, else D3M_FP64 + 1 or D3M_FP32_IR + 1 */
-    int32_t reserved[7];
+    int32_t n_units;          /* pivot units of K (blocks or pieces of blocks) */
+    int32_t n_unit_levels;    /* elimination-tree levels over the units       */
+    int32_t reserved[5];
 } d3m_info;
 
 typedef struct {
@@ -207,11 +213,16 @@ int d3m_kernel_stats(d3m_handle h, int kernel, int reset, int64_t *launches,
  *                        followed by the position lists
  *   D3M_EXPORT_KD        complex128 [m][m] domain matrix K_D^(index) in
  *                        global-LM order (after d3m_factor, FP64 only)
- *   D3M_EXPORT_KFACTOR   the factor of -K in elimination-position order:
- *                        int32 [n_lm] perm-within-block, complex128 [n_lm]
- *                        D diagonal, complex128 [n_lm] D sub-diagonal, then
- *                        complex128 dense [n_lm][n_lm] unit lower L
- *                        (row-major); small problems only
+ *   D3M_EXPORT_KFACTOR   the factor of -K over the pivot units in
+ *                        elimination order (units are consecutive rows of
+ *                        the blocks in D3M_EXPORT_ORDER): int32 n_units,
+ *                        int32 [n_units] unit sizes, int32 [n_lm] perm
+ *                        within the unit, complex128 [n_lm] D diagonal,
+ *                        complex128 [n_lm] D sub-diagonal (first row of a
+ *                        2x2 pivot), then complex128 [n_lm][n_lm] row-major
+ *                        unit lower L whose diagonal unit blocks are L_jj and
+ *                        whose off-diagonal unit blocks are L-hat_ij (rows in
+ *                        the unit's original order); small problems only
  *   D3M_EXPORT_LAMBDA    complex128 [nrhs][n_lm] multipliers of the last
  *                        solve in global LM order                           */
 #define D3M_EXPORT_EDGES      1

@@ -44,7 +44,8 @@ class d3m_mesh(C.Structure):
 class d3m_options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("quad_points", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
-                ("use_graph", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class d3m_info(C.Structure):
@@ -53,7 +54,8 @@ class d3m_info(C.Structure):
                 ("n_levels", C.c_int32), ("factor_bytes", C.c_int64), ("device_bytes", C.c_int64),
                 ("flops_domain", C.c_double), ("flops_block_ldlt", C.c_double),
                 ("flops_update_gemm", C.c_double), ("solve_bytes", C.c_double),
-                ("factored", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("factored", C.c_int32), ("n_units", C.c_int32), ("n_unit_levels", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class d3m_solve_info(C.Structure):
@@ -115,7 +117,7 @@ class Solver:
     """One decomposed problem on the GPU (a d3m_handle)."""
 
     def __init__(self, xyz, tets, part, eps_r, k, alpha, *, host_only=False, profile=False,
-                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10):
+                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10, pivot_scope=0):
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int64)
         self._part = np.ascontiguousarray(part, dtype=np.int32)
@@ -130,6 +132,7 @@ class Solver:
         opt.quad_points = int(quad_points)
         opt.ir_tol = float(ir_tol)
         opt.ir_max_iter = int(ir_max_iter)
+        opt.pivot_scope = int(pivot_scope)
         a = complex(alpha)
         h = _h()
         _check(_lib.d3m_setup(C.byref(mesh), _ptr(self._part, C.c_int32), _ptr(eps, C.c_double),
@@ -264,9 +267,12 @@ class Solver:
             return v.reshape(m, m).copy()
         if what == "kfactor":
             n = self.info["n_lm"]
-            perm = buf[:4 * n].view(np.int32).copy()
-            rest = buf[4 * n:].view(np.complex128)
-            return perm, rest[:n].copy(), rest[n:2 * n].copy(), rest[2 * n:].reshape(n, n).copy()
+            nu = int(buf[:4].view(np.int32)[0])
+            sizes = buf[4:4 + 4 * nu].view(np.int32).copy()
+            o = 4 + 4 * nu
+            perm = buf[o:o + 4 * n].view(np.int32).copy()
+            rest = buf[o + 4 * n:].view(np.complex128)
+            return sizes, perm, rest[:n].copy(), rest[n:2 * n].copy(), rest[2 * n:].reshape(n, n).copy()
         if what == "lambda":
             return buf.view(np.complex128).reshape(int(index), -1).copy()
         return buf

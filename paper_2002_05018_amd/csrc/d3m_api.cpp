@@ -361,8 +361,9 @@ int factor_impl(d3m_problem *h, hipStream_t s) {
             } else {
                 int pos = -1;
                 for (size_t j = 0; j < pl.drow_k.size(); ++j) if (pl.drow_k[j] == t.drow) pos = (int)j;
-                where = "block at position " + std::to_string(pos) + " (canonical " +
-                        std::to_string(pos >= 0 ? h->bo.order[pos] : -1) + ")";
+                where = "unit " + std::to_string(pos) + " of block " +
+                        std::to_string(pos >= 0 ? pl.unit_block[pos] : -1) + " (rows from " +
+                        std::to_string(pos >= 0 ? pl.unit_off[pos] : -1) + ")";
             }
             return fail(D3M_ESINGULAR, "singular pivot block: " + where + ", column " + std::to_string(status[i] - 1));
         }
@@ -510,7 +511,7 @@ int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r, do
         h->eps.assign(eps_r, eps_r + mesh->n_tets);
         build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
         order_blocks(h->bo, h->dc, h->mesh);
-        build_plan(h->pl, h->dc, h->bo);
+        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {
@@ -703,6 +704,8 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->flops_update_gemm = h->pl.flops_update;
     info->solve_bytes = h->pl.solve_bytes;
     info->factored = h->factored;
+    info->n_units = h->pl.k_units;
+    info->n_unit_levels = h->pl.k_levels;
     return D3M_OK;
 }
 
@@ -795,36 +798,33 @@ int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf, int64
             hipMemcpy(doff.data(), h->D.doff, pl.d_rows * 16, hipMemcpyDeviceToHost) != hipSuccess ||
             hipMemcpy(piv.data(), h->D.piv, pl.d_rows * 4, hipMemcpyDeviceToHost) != hipSuccess)
             return fail(D3M_EHIP, "copy of the pivot data failed");
-        const int nb = dc.nblk;
-        std::vector<i64> off(nb + 1, 0);
-        std::vector<int> nsz(nb);
-        for (int j = 0; j < nb; ++j) {
-            int b = h->bo.order[j];
-            nsz[j] = (int)(dc.blk_start[b + 1] - dc.blk_start[b]);
-            off[j + 1] = off[j] + nsz[j];
-        }
+        const int nu = pl.k_units;
+        std::vector<i64> off(nu + 1, 0);
+        for (int j = 0; j < nu; ++j) off[j + 1] = off[j] + pl.unit_n[j];
+        int32_t nu32 = nu;
+        put(&nu32, 4);
+        put(pl.unit_n.data(), (size_t)nu * 4);
         std::vector<int32_t> pv(n);
         std::vector<double2> d0(n), d1(n);
-        for (int j = 0; j < nb; ++j)
-            for (int r = 0; r < nsz[j]; ++r) {
+        for (int j = 0; j < nu; ++j)
+            for (int r = 0; r < pl.unit_n[j]; ++r) {
                 pv[off[j] + r] = perm[pl.drow_k[j] + r];
                 d0[off[j] + r] = dd[pl.drow_k[j] + r];
-                // sub-diagonal of D: only on the first row of a 2x2 pivot
                 d1[off[j] + r] = piv[pl.drow_k[j] + r] == 1 ? doff[pl.drow_k[j] + r] : make_double2(0, 0);
             }
         put(pv.data(), n * 4);
         put(d0.data(), n * 16);
         put(d1.data(), n * 16);
         std::vector<double2> L((size_t)n * n, make_double2(0, 0));
-        for (int j = 0; j < nb; ++j) {
-            std::vector<int> rows{j};
-            rows.insert(rows.end(), h->bo.strct[j].begin(), h->bo.strct[j].end());
-            for (size_t ii = 0; ii < rows.size(); ++ii) {
-                int i = rows[ii];
-                for (int r = 0; r < nsz[i]; ++r)
-                    for (int c = 0; c < nsz[j]; ++c) {
+        for (int j = 0; j < nu; ++j) {
+            // rows of panel j: unit j, then the units of its struct
+            const std::vector<int> &ro = pl.krow_off[j];
+            for (size_t ii = 0; ii < ro.size(); ++ii) {
+                int i = ii == 0 ? j : pl.kstruct[j][ii - 1];
+                for (int r = 0; r < pl.unit_n[i]; ++r)
+                    for (int c = 0; c < pl.unit_n[j]; ++c) {
                         if (i == j && r < c) continue;
-                        i64 slot = pl.kcol[j] + (i64)(c / TILE) * pl.kR[j] + pl.krow_off[j][ii] + r / TILE;
+                        i64 slot = pl.kcol[j] + (i64)(c / TILE) * pl.kR[j] + ro[ii] + r / TILE;
                         L[(size_t)(off[i] + r) * n + off[j] + c] = tile_val(slot, r % TILE, c % TILE);
                     }
             }

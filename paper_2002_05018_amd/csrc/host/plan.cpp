@@ -21,9 +21,8 @@ inline int ceil_div(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total - (i64)t * TILE); }
 }  // namespace
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) {
     const int N = dc.N;
-    const int nb = dc.nblk;
     pl = Plan();
 
     // ------------------------------------------------------------ layouts --
@@ -47,11 +46,50 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     }
     pl.m_tiles = slot;
 
-    std::vector<int> nsz(nb);
-    for (int j = 0; j < nb; ++j) {
-        int b = bo.order[j];
-        nsz[j] = (int)(dc.blk_start[b + 1] - dc.blk_start[b]);
+    // Units of the LM Schur complement: the blocks in elimination order, each
+    // split into ceil(n / unit_max) nearly equal consecutive pieces when
+    // unit_max > 0 (the pivot search of step 5 is then restricted to a
+    // piece).  unit_max <= 0 keeps whole blocks.
+    std::vector<int> ublk, uoff, nsz, ufirst(dc.nblk + 1, 0);
+    for (int j = 0; j < (int)bo.order.size(); ++j) {
+        const int b = bo.order[j];
+        const int n = (int)(dc.blk_start[b + 1] - dc.blk_start[b]);
+        const int pieces = unit_max > 0 ? std::max(1, (n + unit_max - 1) / unit_max) : 1;
+        ufirst[j] = (int)ublk.size();
+        int o = 0;
+        for (int c = 0; c < pieces; ++c) {
+            const int sz = n / pieces + (c < n % pieces ? 1 : 0);
+            ublk.push_back(b);
+            uoff.push_back(o);
+            nsz.push_back(sz);
+            o += sz;
+        }
     }
+    ufirst[bo.order.size()] = (int)ublk.size();
+    const int nb = (int)ublk.size();
+    std::vector<std::vector<int>> ustruct(nb);
+    std::vector<int> ulevel(nb, 0), upos_block(nb);
+    for (int j = 0; j < (int)bo.order.size(); ++j)
+        for (int u = ufirst[j]; u < ufirst[j + 1]; ++u) {
+            upos_block[u] = j;
+            for (int v = u + 1; v < ufirst[j + 1]; ++v) ustruct[u].push_back(v);
+            for (int i : bo.strct[j])
+                for (int v = ufirst[i]; v < ufirst[i + 1]; ++v) ustruct[u].push_back(v);
+            for (size_t x = 0; x < ustruct[u].size(); ++x)
+                if (ustruct[u][x] <= u || (x && ustruct[u][x] <= ustruct[u][x - 1]))
+                    throw Error{-1, "internal: unit structure not increasing"};
+        }
+    int nlev = 0;
+    for (int u = 0; u < nb; ++u) {
+        if (!ustruct[u].empty()) ulevel[ustruct[u][0]] = std::max(ulevel[ustruct[u][0]], ulevel[u] + 1);
+        nlev = std::max(nlev, ulevel[u] + 1);
+    }
+    pl.k_units = nb;
+    pl.k_levels = nlev;
+    pl.unit_block = ublk;
+    pl.unit_off = uoff;
+    pl.unit_n = nsz;
+    pl.kstruct = ustruct;
     pl.kt.resize(nb); pl.kcol.resize(nb); pl.kR.resize(nb); pl.krow_off.resize(nb);
     pl.tt_k.resize(nb); pl.drow_k.resize(nb);
     for (int j = 0; j < nb; ++j) pl.kt[j] = ceil_div(nsz[j], TILE);
@@ -61,7 +99,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         ro.clear();
         int r = pl.kt[j];
         ro.push_back(0);
-        for (int i : bo.strct[j]) { ro.push_back(r); r += pl.kt[i]; }
+        for (int i : ustruct[j]) { ro.push_back(r); r += pl.kt[i]; }
         pl.kR[j] = r;
         pl.kcol[j] = slot;
         slot += (i64)r * pl.kt[j];
@@ -82,7 +120,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     // row-tile offset of block i inside the panel of block column j
     auto rowoff = [&](int j, int i) -> int {
         if (i == j) return 0;
-        const auto &s = bo.strct[j];
+        const auto &s = ustruct[j];
         auto it = std::lower_bound(s.begin(), s.end(), i);
         if (it == s.end() || *it != i) throw Error{-1, "internal: block not in struct"};
         return pl.krow_off[j][1 + (it - s.begin())];
@@ -159,11 +197,11 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     // -K(i, j) = sum over subdomains d holding both blocks of the trailing
     // block of M_d at the rows of block i and the columns of block j
     for (int j = 0; j < nb; ++j) {
-        int Q = bo.order[j];
+        int Q = ublk[j];
         std::vector<int> rows_blocks{j};
-        rows_blocks.insert(rows_blocks.end(), bo.strct[j].begin(), bo.strct[j].end());
+        rows_blocks.insert(rows_blocks.end(), ustruct[j].begin(), ustruct[j].end());
         for (int i : rows_blocks) {
-            int P = bo.order[i];
+            int P = ublk[i];
             std::vector<int> common;
             for (int dP : {dc.blk_p[P], dc.blk_q[P]})
                 for (int dQ : {dc.blk_p[Q], dc.blk_q[Q]})
@@ -182,8 +220,8 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
                         auto oP = std::lower_bound(S.blocks.begin(), S.blocks.end(), P) - S.blocks.begin();
                         auto oQ = std::lower_bound(S.blocks.begin(), S.blocks.end(), Q) - S.blocks.begin();
                         t.mbase[c] = pl.m_base[d];
-                        t.row0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oP] + (i64)a * TILE);
-                        t.col0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oQ] + (i64)b * TILE);
+                        t.row0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oP] + uoff[i] + (i64)a * TILE);
+                        t.col0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oQ] + uoff[j] + (i64)b * TILE);
                     }
                     pl.asmb.push_back(t);
                 }
@@ -191,10 +229,10 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     }
 
     // ------------------------------------- step 5 (block LDL^T of -K) plan --
-    std::vector<std::vector<int>> by_level(bo.n_levels);
-    for (int j = 0; j < nb; ++j) by_level[bo.level[j]].push_back(j);
+    std::vector<std::vector<int>> by_level(nlev);
+    for (int j = 0; j < nb; ++j) by_level[ulevel[j]].push_back(j);
     const int LDS_MAX_N = 136;
-    for (int L = 0; L < bo.n_levels; ++L) {
+    for (int L = 0; L < nlev; ++L) {
         const auto &J = by_level[L];
         FactorStep st;
         st.bk0 = (i64)pl.bk.size();
@@ -219,7 +257,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         st.sc0 = (i64)pl.scale.size();
         for (int j : J) {
             int tj = pl.kt[j];
-            for (int i : bo.strct[j])
+            for (int i : ustruct[j])
                 for (int a = 0; a < pl.kt[i]; ++a)
                     for (int b = 0; b < tj; ++b) {
                         pl.gemm.push_back({E(ARR_KX, kslot(j, i, a, b)), (int32_t)pl.pairs.size(), tj});
@@ -236,7 +274,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
                         pl.scale.push_back(s);
                     }
             double pf = 0.0;
-            for (int i : bo.strct[j]) pf += 8.0 * nsz[i] * (double)nsz[j] * nsz[j] / 2.0;
+            for (int i : ustruct[j]) pf += 8.0 * nsz[i] * (double)nsz[j] * nsz[j] / 2.0;
             st.pan_flops += pf;
             pl.flops_s3 += pf;
         }
@@ -246,9 +284,9 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         // written by exactly one work-group (deterministic, atomic-free)
         std::map<std::pair<int, int>, std::vector<int>> targets;
         for (int j : J)
-            for (size_t x = 0; x < bo.strct[j].size(); ++x)
+            for (size_t x = 0; x < ustruct[j].size(); ++x)
                 for (size_t y = 0; y <= x; ++y)
-                    targets[{bo.strct[j][x], bo.strct[j][y]}].push_back(j);
+                    targets[{ustruct[j][x], ustruct[j][y]}].push_back(j);
         st.up0 = (i64)pl.gemm.size();
         for (auto &kv : targets) {
             int i = kv.first.first, k = kv.first.second;
@@ -323,9 +361,9 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     std::vector<i64> &kvrow_of_lm = pl.lm_vrow;
     kvrow_of_lm.assign(dc.n_lm, -1);
     for (int j = 0; j < nb; ++j) {
-        int P = bo.order[j];
-        for (i64 l = dc.blk_start[P]; l < dc.blk_start[P + 1]; ++l)
-            kvrow_of_lm[l] = pl.vk[j] * TILE + (l - dc.blk_start[P]);
+        int P = ublk[j];
+        for (int o = 0; o < nsz[j]; ++o)
+            kvrow_of_lm[dc.blk_start[P] + uoff[j] + o] = pl.vk[j] * TILE + o;
     }
     std::vector<int64_t> &hmap = pl.h_map;
     hmap.assign(pl.v_tiles_k * TILE * 2, -1);
@@ -374,7 +412,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         pl.s1_fwd.push_back(st);
     }
     // K forward / backward
-    for (int L = 0; L < bo.n_levels; ++L) {
+    for (int L = 0; L < nlev; ++L) {
         SolveStep st;
         st.dg0 = (i64)pl.vdiag.size();
         for (int j : by_level[L]) {
@@ -389,7 +427,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         st.ndg = (i64)pl.vdiag.size() - st.dg0;
         std::map<int, std::vector<int>> targets;
         for (int j : by_level[L])
-            for (int i : bo.strct[j]) targets[i].push_back(j);
+            for (int i : ustruct[j]) targets[i].push_back(j);
         st.up0 = (i64)pl.vupd.size();
         st.up_mode = 0;
         for (auto &kv : targets) {
@@ -407,7 +445,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         st.nup = (i64)pl.vupd.size() - st.up0;
         pl.k_fwd.push_back(st);
     }
-    for (int L = bo.n_levels - 1; L >= 0; --L) {
+    for (int L = nlev - 1; L >= 0; --L) {
         SolveStep st;
         st.up_first = true;
         st.up0 = (i64)pl.vupd.size();
@@ -415,7 +453,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
         for (int j : by_level[L])
             for (int b = 0; b < pl.kt[j]; ++b) {
                 VUpdTask u{V(V_KACC, pl.vk[j] + b), (int32_t)pl.vpairs.size(), 0};
-                for (int i : bo.strct[j])
+                for (int i : ustruct[j])
                     for (int a = 0; a < pl.kt[i]; ++a) {
                         pl.vpairs.push_back({E(ARR_KL, kslot(j, i, a, b)), V(V_KX, pl.vk[i] + a)});
                         ++u.np;
@@ -491,7 +529,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo) {
     }
     for (int j = 0; j < nb; ++j) {
         ent += (i64)nsz[j] * (nsz[j] - 1) / 2;
-        for (int i : bo.strct[j]) ent += (i64)nsz[i] * nsz[j];
+        for (int i : ustruct[j]) ent += (i64)nsz[i] * nsz[j];
     }
     pl.factor_entries = ent;
     pl.solve_bytes = 2.0 * 16.0 * (double)ent;

@@ -35,6 +35,11 @@ struct Plan {
     std::vector<i64> m_base;           // tile slot of tile (0,0) of each subdomain in ARR_M
     i64 m_tiles = 0;
     // ---- LM Schur complement (-K), elimination-position order -----------
+    // Units are the blocks of K in elimination order, or pieces of them
+    // (consecutive rows of one block) when the pivot scope is restricted.
+    int k_units = 0, k_levels = 0;
+    std::vector<int> unit_block, unit_off, unit_n;
+    std::vector<std::vector<int>> kstruct;  // struct of every unit (unit indices)
     std::vector<int> kt;               // tiles per block
     std::vector<i64> kcol;             // slot of the panel's tile (0,0) for each block column
     std::vector<int> kR;               // row tiles of each block-column panel
@@ -75,6 +80,6 @@ struct Plan {
     i64 factor_entries = 0;
 };
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo);
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max);
 
 }  // namespace d3m

@@ -26,12 +26,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cfms(double2 a, double2 b, double2 c) {
     return make_double2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
 }
+// a - b*c with fused multiply-adds
+__device__ __forceinline__ double2 cfma_neg(double2 a, double2 b, double2 c) {
+    return make_double2(fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y)));
+}
 // 1/z from the definition conj(z)/|z|^2 (scaled to avoid overflow)
 __device__ __forceinline__ double2 crecip(double2 z) {
-    double s = fmax(fabs(z.x), fabs(z.y));
-    double xr = z.x / s, xi = z.y / s;
-    double den = (xr * xr + xi * xi) * s;
-    return make_double2(xr / den, -xi / den);
+    const double s = fmax(fabs(z.x), fabs(z.y));
+    const double is = 1.0 / s;
+    const double xr = z.x * is, xi = z.y * is;
+    const double id = 1.0 / ((xr * xr + xi * xi) * s);
+    return make_double2(xr * id, -xi * id);
 }
 __device__ __forceinline__ double cabs1(double2 z) { return fabs(z.x) + fabs(z.y); }
 

@@ -221,6 +221,324 @@ __global__ void bk_kernel(const BkTask *tasks, Bases bases, DArrays D, int *stat
     }
 }
 
+// ------------------------------------- Bunch-Kaufman, register variant --
+// Same pivoting rule and outputs as bk_kernel, for blocks of order <= NM.
+// The whole block is held as a full symmetric square in registers: thread
+// (pr, qc) owns rows pr + TR*a and columns qc + TC*b.  Each pivot step
+// broadcasts the pivot column and the rows being interchanged through small
+// LDS vectors, so a step costs two or three work-group barriers and no
+// serial per-thread loops.  L^{-1} is accumulated alongside the elimination
+// (Z <- (I - l_k e_k^T) Z, with the row interchanges applied to Z as they are
+// to L) in owner-exclusive LDS storage, giving TT = L^{-1} P^T at the end.
+// wave-uniform values kept in scalar registers
+__device__ __forceinline__ double uni(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 uni2(double2 z) { return make_double2(uni(z.x), uni(z.y)); }
+
+// Wave-wide maximum of a double with DPP row shifts and row broadcasts
+// (no LDS traffic); every lane receives the result.
+__device__ __forceinline__ double dpp_max_step(double v, int ctrl, int row_mask) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    int lo2, hi2;
+    switch (ctrl) {
+    case 0x111: lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x111, 0xf, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x111, 0xf, 0xf, false); break;
+    case 0x112: lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x112, 0xf, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x112, 0xf, 0xf, false); break;
+    case 0x114: lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x114, 0xf, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x114, 0xf, 0xf, false); break;
+    case 0x118: lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x118, 0xf, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x118, 0xf, 0xf, false); break;
+    case 0x142: lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x142, 0xa, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x142, 0xa, 0xf, false); break;
+    default:    lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x143, 0xc, 0xf, false);
+                hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x143, 0xc, 0xf, false); break;
+    }
+    (void)row_mask;
+    return fmax(v, __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2));
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = dpp_max_step(v, 0x111, 0xf);  // row_shr:1
+    v = dpp_max_step(v, 0x112, 0xf);  // row_shr:2
+    v = dpp_max_step(v, 0x114, 0xf);  // row_shr:4
+    v = dpp_max_step(v, 0x118, 0xf);  // row_shr:8
+    v = dpp_max_step(v, 0x142, 0xa);  // row_bcast:15
+    v = dpp_max_step(v, 0x143, 0xc);  // row_bcast:31
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Arg-max of |col[i]| = |Re|+|Im| over lo <= i < hi, i != skip (64 rows, one
+// per lane), computed by every wave on its own: wave maximum, then the lowest
+// row holding it (ballot).  Returns value -1 when the range is empty.
+__device__ __forceinline__ void wave_argmax_col(const double2 *col, int lo, int hi, int skip, double &mv, int &mi) {
+    const int i = threadIdx.x & 63;
+    const bool act = i >= lo && i < hi && i != skip;
+    const double v = act ? cabs1(col[i]) : -1.0;
+    const double m = wave_max(v);
+    const unsigned long long b = __ballot(act && v == m);
+    mv = m;
+    mi = b ? (__ffsll((long long)b) - 1) : -1;
+}
+
+// Bunch-Kaufman on a block of order <= 64 (same pivoting rule and outputs as
+// bk_kernel).  The block is a full symmetric square in registers: thread
+// (pr, qc) of a TR x TC grid owns rows pr + TR a and columns qc + TC b.  So is
+// Z = L^{-1}, accumulated alongside the elimination (Z <- (I - l_k e_k^T) Z,
+// with the row interchanges applied to Z as to L).  Each pivot step
+// publishes the pivot column (and column r, and the rows that move) through
+// small LDS vectors; every wave reduces them itself with DPP, so a step costs
+// two or three work-group barriers.
+template <typename T2, int TR, int TC>
+__global__ __launch_bounds__(TR * TC) void bk64_kernel(const BkTask *tasks, Bases bases, DArrays D, int *status) {
+    constexpr int NM = 64, NT = TR * TC, RA = NM / TR, RB = NM / TC;
+    __shared__ double2 colk[NM], colr[NM], rkk[NM], rp[NM], zk[NM], zkk[NM], zp[NM];
+    __shared__ double2 sd[NM], sdoff[NM], sdinv[NM], sdinvoff[NM];  // D outputs, flushed at the end
+    __shared__ int sperm[NM], spiv[NM];
+
+    const BkTask tk = tasks[blockIdx.x];
+    const int n = tk.n, t = threadIdx.x, pr = t % TR, qc = t / TR;
+    double2 a[RA][RB], z[RA][RB];
+    {
+        const T2 *src = enc_ptr<T2>(bases, tk.a);
+#pragma unroll
+        for (int aa = 0; aa < RA; ++aa)
+#pragma unroll
+            for (int bb = 0; bb < RB; ++bb) {
+                const int i = pr + TR * aa, j = qc + TC * bb;
+                a[aa][bb] = make_double2(0, 0);
+                if (i < n && j < n) a[aa][bb] = to_d2(src[tile_elem(i > j ? i : j, i > j ? j : i, tk.ldt)]);
+                z[aa][bb] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+            }
+    }
+    if (t < NM) sperm[t] = t;
+    __syncthreads();
+
+    int k = 0;
+    bool singular = false;
+    while (k < n) {
+        const int qk = k % TC, bk = k / TC;
+        if (qc == qk) {
+#pragma unroll
+            for (int bb = 0; bb < RB; ++bb)
+                if (bb == bk) {
+#pragma unroll
+                    for (int aa = 0; aa < RA; ++aa) colk[pr + TR * aa] = a[aa][bb];
+                }
+        }
+        __syncthreads();
+        double lam1;
+        int r;
+        wave_argmax_col(colk, k + 1, n, -1, lam1, r);
+        if (lam1 < 0.0 || r < 0) { lam1 = 0.0; r = k; }
+        const double akk = cabs1(colk[k]);
+        int size = 1, p = k;
+        if (!(fmax(akk, lam1) > 0.0)) {
+            singular = true;
+        } else if (!(akk >= kAlphaBK * lam1) && r > k) {
+            const int qr = r % TC, br = r / TC;
+            if (qc == qr) {
+#pragma unroll
+                for (int bb = 0; bb < RB; ++bb)
+                    if (bb == br) {
+#pragma unroll
+                        for (int aa = 0; aa < RA; ++aa) colr[pr + TR * aa] = a[aa][bb];
+                    }
+            }
+            __syncthreads();
+            double sigma;
+            int dummy;
+            wave_argmax_col(colr, k, n, r, sigma, dummy);
+            const double arr = cabs1(colr[r]);
+            if (akk * sigma >= kAlphaBK * lam1 * lam1) { size = 1; p = k; }
+            else if (arr >= kAlphaBK * sigma) { size = 1; p = r; }
+            else { size = 2; p = r; }
+        }
+        if (singular) break;
+        const int kk = k + size - 1;
+        const bool swap = p != kk;
+        // ---- publish the rows that move (rows kk, p of A and Z; row k of Z)
+        if (swap && pr == kk % TR) {
+            const int ak = kk / TR;
+#pragma unroll
+            for (int aa = 0; aa < RA; ++aa)
+                if (aa == ak) {
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) { rkk[qc + TC * bb] = a[aa][bb]; zkk[qc + TC * bb] = z[aa][bb]; }
+                }
+        }
+        if ((swap || size == 2) && pr == p % TR) {
+            const int ap = p / TR;
+#pragma unroll
+            for (int aa = 0; aa < RA; ++aa)
+                if (aa == ap) {
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) { rp[qc + TC * bb] = a[aa][bb]; zp[qc + TC * bb] = z[aa][bb]; }
+                }
+        }
+        if ((size == 2 || !swap) && pr == k % TR) {
+            const int ak = k / TR;
+#pragma unroll
+            for (int aa = 0; aa < RA; ++aa)
+                if (aa == ak) {
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) zk[qc + TC * bb] = z[aa][bb];
+                }
+        }
+        __syncthreads();
+        auto pi = [&](int x) { return !swap ? x : (x == kk ? p : (x == p ? kk : x)); };
+        // ---- symmetric interchange kk <-> p (rows of A, L and Z; columns of A)
+        if (swap) {
+#pragma unroll
+            for (int aa = 0; aa < RA; ++aa) {
+                const int i = pr + TR * aa;
+                if (i == kk || i == p) {
+                    const double2 *src = (i == kk) ? rp : rkk;
+                    const double2 *zsrc = (i == kk) ? zp : zkk;
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) {
+                        const int j = qc + TC * bb;
+                        a[aa][bb] = src[pi(j)];
+                        if (j < k) z[aa][bb] = zsrc[j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int bb = 0; bb < RB; ++bb) {
+                const int j = qc + TC * bb;
+                if (j == kk || j == p) {
+                    const double2 *src = (j == kk) ? rp : rkk;
+#pragma unroll
+                    for (int aa = 0; aa < RA; ++aa) {
+                        const int i = pr + TR * aa;
+                        if (i != kk && i != p) a[aa][bb] = src[i];
+                    }
+                }
+            }
+            if (t == 0) { int sw = sperm[kk]; sperm[kk] = sperm[p]; sperm[p] = sw; }
+        }
+        // ---- pivot block and multipliers.  New column k: c0[pi(.)] with
+        // c0 = row p for a 1x1 pivot with interchange, else column k; new
+        // column k+1 (2x2): row p [pi(.)].
+        const bool two = size == 2;
+        const double2 *c0 = (!two && swap) ? rp : colk;
+        const double2 ea = uni2(c0[pi(k)]);
+        double2 e11, e12, e22, eb = make_double2(0, 0), ec = make_double2(0, 0);
+        if (!two) {
+            e11 = uni2(crecip(ea));
+            e12 = e22 = make_double2(0, 0);
+        } else {
+            eb = uni2(colk[p]);
+            ec = uni2(rp[p]);
+            const double2 idet = crecip(csub(cmul(ea, ec), cmul(eb, eb)));
+            e11 = uni2(cmul(ec, idet));
+            e22 = uni2(cmul(ea, idet));
+            e12 = uni2(make_double2(-(eb.x * idet.x - eb.y * idet.y), -(eb.x * idet.y + eb.y * idet.x)));
+        }
+        // column values of the owned columns and rows of Z'(k,.), Z'(k+1,.)
+        const double2 *z0row = (!two && swap) ? zp : zk;
+        double2 xc0[RB], xc1[RB], zr0[RB], zr1[RB];
+#pragma unroll
+        for (int bb = 0; bb < RB; ++bb) {
+            const int j = qc + TC * bb;
+            const bool trail = j > kk && j < n;
+            xc0[bb] = trail ? c0[pi(j)] : make_double2(0, 0);
+            xc1[bb] = (trail && two) ? rp[pi(j)] : make_double2(0, 0);
+            zr0[bb] = (j == k) ? make_double2(1.0, 0.0) : (j < k ? z0row[j] : make_double2(0, 0));
+            zr1[bb] = two ? ((j == k + 1) ? make_double2(1.0, 0.0) : (j < k ? zp[j] : make_double2(0, 0)))
+                          : make_double2(0, 0);
+        }
+        // ---- rank-1 / rank-2 update.  For a column j only one of A (trailing,
+        // j > kk) and Z (eliminated, j <= kk) changes; column groups bb are
+        // uniform except the one holding the pivot columns.
+#pragma unroll
+        for (int aa = 0; aa < RA; ++aa) {
+            const int i = pr + TR * aa;
+            if (i > kk && i < n) {
+                const double2 x0 = c0[pi(i)];
+                if (!two) {
+                    const double2 l0 = cmul(x0, e11);
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) {
+                        const int j = qc + TC * bb;
+                        if (TC * bb > k) {
+                            a[aa][bb] = cfma_neg(a[aa][bb], l0, xc0[bb]);
+                        } else if (TC * bb + TC - 1 < k) {
+                            z[aa][bb] = cfma_neg(z[aa][bb], l0, zr0[bb]);
+                        } else {
+                            if (j > k) a[aa][bb] = cfma_neg(a[aa][bb], l0, xc0[bb]);
+                            else z[aa][bb] = cfma_neg(z[aa][bb], l0, zr0[bb]);
+                            if (j == k) a[aa][bb] = l0;
+                        }
+                    }
+                } else {
+                    const double2 x1 = rp[pi(i)];
+                    const double2 l0 = cadd(cmul(x0, e11), cmul(x1, e12));
+                    const double2 l1 = cadd(cmul(x0, e12), cmul(x1, e22));
+#pragma unroll
+                    for (int bb = 0; bb < RB; ++bb) {
+                        const int j = qc + TC * bb;
+                        if (TC * bb > kk) {
+                            a[aa][bb] = cfma_neg(cfma_neg(a[aa][bb], l0, xc0[bb]), l1, xc1[bb]);
+                        } else if (TC * bb + TC - 1 < k) {
+                            z[aa][bb] = cfma_neg(cfma_neg(z[aa][bb], l0, zr0[bb]), l1, zr1[bb]);
+                        } else {
+                            if (j > kk) a[aa][bb] = cfma_neg(cfma_neg(a[aa][bb], l0, xc0[bb]), l1, xc1[bb]);
+                            else z[aa][bb] = cfma_neg(cfma_neg(z[aa][bb], l0, zr0[bb]), l1, zr1[bb]);
+                            if (j == k) a[aa][bb] = l0;
+                            if (j == k + 1) a[aa][bb] = l1;
+                        }
+                    }
+                }
+            }
+            if (two && i == k + 1) {
+#pragma unroll
+                for (int bb = 0; bb < RB; ++bb)
+                    if (qc + TC * bb == k) a[aa][bb] = make_double2(0, 0);
+            }
+        }
+        if (t == 0) {
+            sd[k] = ea; sdoff[k] = eb; sdinv[k] = e11; sdinvoff[k] = e12; spiv[k] = two ? 1 : 0;
+            if (two) { sd[k + 1] = ec; sdoff[k + 1] = eb; sdinv[k + 1] = e22; sdinvoff[k + 1] = e12; spiv[k + 1] = -1; }
+        }
+        __syncthreads();
+        k += size;
+    }
+    if (singular) {
+        if (t == 0) status[tk.status] = k + 1;
+        return;
+    }
+    const int64_t dr = tk.drow;
+    if (t < n) {
+        D.d[dr + t] = sd[t]; D.doff[dr + t] = sdoff[t];
+        D.dinv[dr + t] = sdinv[t]; D.dinvoff[dr + t] = sdinvoff[t];
+        D.piv[dr + t] = spiv[t];
+        D.perm[dr + t] = sperm[t];
+    }
+    // ---- outputs: unit lower L and TT = Z P^T (zero elsewhere in the tile)
+    T2 *lout = enc_ptr<T2>(bases, tk.l);
+    T2 *tt = enc_ptr<T2>(bases, tk.tt);
+#pragma unroll
+    for (int aa = 0; aa < RA; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < RB; ++bb) {
+            const int i = pr + TR * aa, j = qc + TC * bb;
+            if (i < n && j < n && i >= j)
+                lout[tile_elem(i, j, tk.ldt)] = from_d2<T2>(i == j ? make_double2(1.0, 0.0) : a[aa][bb]);
+            // TT[i][perm[j]] = Z[i][j]; columns perm[j] for j >= n are padding
+            const int col = j < n ? sperm[j] : j;
+            const double2 zv = (i < n && j < n && i >= j) ? z[aa][bb] : make_double2(0, 0);
+            tt[col * 64 + i] = from_d2<T2>(zv);
+        }
+}
+
 // ------------------------------------------------- complex GEMM (MFMA) --
 // C (=|-=) sum_p A_p B_p^T for 64x64 complex tiles, 4M (four real MFMAs per
 // complex product), 256 threads: wave w owns the 32x32 quadrant
@@ -379,13 +697,21 @@ size_t bk_lds_bytes(int n, int nthr, bool lds) {
     return (a + 2 * (size_t)nthr) * sizeof(double2) + 16 * sizeof(double) + 16 * sizeof(int) + (size_t)nthr * sizeof(int);
 }
 
+#ifndef BK64_TR
+#define BK64_TR 32  // 32 x 16 threads: 8 elements of A and of Z per thread
+#define BK64_TC 16
+#endif
 template <typename T>
 hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &b, const DArrays &D, int *status,
                      double2 *scratch, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
+    if (maxn <= 64) {
+        hipLaunchKernelGGL((bk64_kernel<T2, BK64_TR, BK64_TC>), dim3((unsigned)ntask), dim3(BK64_TR * BK64_TC), 0, s,
+                           tasks, b, D, status);
+        return hipGetLastError();
+    }
     int nthr = ((maxn + 63) / 64) * 64;
-    if (nthr < 64) nthr = 64;
     if (nthr > 1024) return hipErrorInvalidValue;
     bool lds = bk_lds_bytes(maxn, nthr, true) <= 160 * 1024 - 256;
     size_t shm = bk_lds_bytes(maxn, nthr, lds);

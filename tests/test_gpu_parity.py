@@ -71,33 +71,42 @@ def test_fp64_field_multipliers_domain_matrices(name):
             assert _rel(s.export("kd", d), o.dm.KD[d]) <= 1e-12, d
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cross_lines_2x2x2", "block_208_global_bk"])
-def test_factor_reconstructs_minus_K(name):
-    prob, s, o, f, Eo, lamo = _pair(name)
+@pytest.mark.parametrize("name,scope", [("cfg1", 0), ("cross_lines_2x2x2", 0), ("block_208_global_bk", 0),
+                                        ("cfg1", 1), ("block_208_global_bk", 1)])
+def test_factor_reconstructs_minus_K(name, scope):
+    """P L D L^T P^T over the pivot units must equal -K (oracle) in the
+    library's block order; scope 1 restricts pivots to whole blocks (the
+    paper's Algorithm 1), scope 0 to pieces of at most 64 rows."""
+    from paper_2002_05018_amd import Solver
+    prob, _, o, f, Eo, lamo = _pair(name)
+    s = Solver.from_problem(prob, pivot_scope=scope)
     s.factor("fp64")
-    perm, d0, d1, L = s.export("kfactor")
+    sizes, perm, d0, d1, L = s.export("kfactor")
     order = s.export("order")
     dec = o.dec
-    sizes = [int(dec.block_start[b + 1] - dec.block_start[b]) for b in order]
+    if scope == 1:
+        assert list(sizes) == [int(dec.block_start[b + 1] - dec.block_start[b]) for b in order]
+    else:
+        assert max(sizes) <= 64
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
     n = off[-1]
     P = np.zeros((n, n))
-    Lg = L.copy()
     for j in range(len(sizes)):
         sj = slice(off[j], off[j + 1])
-        P[off[j] + perm[sj], off[j] + np.arange(sizes[j])] = 1.0  # P_j
-    # global factor: L_ij = P_i^T Lhat_ij for the off-diagonal blocks
+        P[off[j] + perm[sj], off[j] + np.arange(sizes[j])] = 1.0
+    Lg = L.copy()
     for i in range(len(sizes)):
         si = slice(off[i], off[i + 1])
-        Pi = P[si, si]
         for j in range(i):
             sj = slice(off[j], off[j + 1])
-            Lg[si, sj] = Pi.T @ L[si, sj]
+            Lg[si, sj] = P[si, si].T @ L[si, sj]  # L_ij = P_i^T Lhat_ij
     D = np.diag(d0) + np.diag(d1[:-1], -1) + np.diag(d1[:-1], 1)
     rec = P @ Lg @ D @ Lg.T @ P.T
     idx = np.concatenate([np.arange(dec.block_start[b], dec.block_start[b + 1]) for b in order])
     K = o.dm.assemble_dense()[np.ix_(idx, idx)]
     assert np.linalg.norm(rec + K) <= 1e-12 * np.linalg.norm(K)
+    E = s.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert _rel(E, Eo) <= 1e-10
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cross_lines_2x2x2", "uneven_1x3x2"])

@@ -76,3 +76,18 @@ def test_probe(pair):
         for a in range(6):
             Pm[:, edges[m, a]] += coef[m, a]
         assert np.abs(Pm - P[m]).max() <= 1e-12 * np.abs(P[m]).max()
+
+
+def test_pivot_units_and_levels():
+    """Pivot units: whole blocks (scope 1) or pieces of at most 64 rows
+    (scope 0); the unit elimination tree must have at least as many levels
+    as the block tree and cover every multiplier once."""
+    from paper_2002_05018_amd import Solver
+    prob = W.make_problem(8, (2, 2, 1), eps=("uniform", 1, 4), k=2 * math.pi, seed=3)
+    whole = Solver.from_problem(prob, host_only=True, pivot_scope=1).info
+    piece = Solver.from_problem(prob, host_only=True, pivot_scope=0).info
+    assert whole["n_units"] == whole["n_blocks"]
+    assert piece["n_units"] > piece["n_blocks"]  # blocks of 208 rows split into 4 pieces
+    assert piece["n_unit_levels"] >= whole["n_unit_levels"] >= 2
+    c1 = Solver.from_problem(W.make_config(1), host_only=True).info
+    assert c1["n_units"] == 4 and c1["n_unit_levels"] == 3
