@@ -393,6 +393,7 @@ int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accu
     for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
     HIPCHK(launch_vgather_h<T>(vb.p[V_KX], vb.p[V_X], h->d_hmap, pl.v_tiles_k * 64, nrhs, s));
     for (const auto &st : pl.k_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
+    HIPCHK(launch_fill_zero<T>(vb.p[V_KACC], pl.v_tiles_k * 64 * nrhs, s));
     for (const auto &st : pl.k_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
     HIPCHK(launch_vscatter_lam<T>(vb.p[V_X], vb.p[V_KX], h->d_lmap, pl.v_tiles_s1 * 64, nrhs, s));
     for (const auto &st : pl.s1_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;

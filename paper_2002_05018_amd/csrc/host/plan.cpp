@@ -445,22 +445,14 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         st.nup = (i64)pl.vupd.size() - st.up0;
         pl.k_fwd.push_back(st);
     }
+    // backward over K, right-looking: after the diagonal solves of a level,
+    // its multipliers are pushed into the accumulators of every descendant
+    // that holds them in its struct, grouped by target (deterministic)
+    std::vector<std::map<int, std::vector<int>>> push(nlev);
+    for (int c = 0; c < nb; ++c)
+        for (int i : ustruct[c]) push[ulevel[i]][c].push_back(i);
     for (int L = nlev - 1; L >= 0; --L) {
         SolveStep st;
-        st.up_first = true;
-        st.up0 = (i64)pl.vupd.size();
-        st.up_mode = 1;
-        for (int j : by_level[L])
-            for (int b = 0; b < pl.kt[j]; ++b) {
-                VUpdTask u{V(V_KACC, pl.vk[j] + b), (int32_t)pl.vpairs.size(), 0};
-                for (int i : ustruct[j])
-                    for (int a = 0; a < pl.kt[i]; ++a) {
-                        pl.vpairs.push_back({E(ARR_KL, kslot(j, i, a, b)), V(V_KX, pl.vk[i] + a)});
-                        ++u.np;
-                    }
-                pl.vupd.push_back(u);
-            }
-        st.nup = (i64)pl.vupd.size() - st.up0;
         st.dg0 = (i64)pl.vdiag.size();
         for (int j : by_level[L]) {
             VDiagTask t{};
@@ -472,6 +464,21 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
             pl.vdiag.push_back(t);
         }
         st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 2;
+        for (auto &kv : push[L]) {
+            const int c = kv.first;
+            for (int b = 0; b < pl.kt[c]; ++b) {
+                VUpdTask u{V(V_KACC, pl.vk[c] + b), (int32_t)pl.vpairs.size(), 0};
+                for (int i : kv.second)
+                    for (int a = 0; a < pl.kt[i]; ++a) {
+                        pl.vpairs.push_back({E(ARR_KL, kslot(c, i, a, b)), V(V_KX, pl.vk[i] + a)});
+                        ++u.np;
+                    }
+                pl.vupd.push_back(u);
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
         pl.k_bwd.push_back(st);
     }
     // S1 backward: first the multiplier rows' contribution, then tile columns

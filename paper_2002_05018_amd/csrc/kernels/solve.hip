@@ -30,65 +30,79 @@ __global__ void vsplit_kernel(T2 *X, const double2 *f, const int64_t *map, int64
 
 // Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y.
 // Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
+// Each TT tile is staged through LDS (row stride 65) and applied to up to 32
+// right-hand sides (blockIdx.y selects the column chunk).
 template <typename T2, bool BWD>
 __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
+    __shared__ T2 Ls[64 * 65];
     const VDiagTask tk = tasks[blockIdx.x];
     const int t = tk.t;
     const T2 *TT = enc_ptr<T2>(b, tk.tt);
     const int64_t vt = 64 * (int64_t)nrhs;
-    if (!BWD) {
-        const T2 *x = vptr<T2>(vb, tk.x, nrhs);
-        T2 *y = vptr<T2>(vb, tk.y, nrhs);
-        T2 *v = vptr<T2>(vb, tk.v, nrhs);
-        for (int bt = 0; bt < t; ++bt)
-            for (int e = threadIdx.x; e < vt; e += blockDim.x) {
+    const int c0 = blockIdx.y * 32;
+    const int ncol = min(32, nrhs - c0);
+    const T2 *xin = BWD ? nullptr : vptr<T2>(vb, tk.x, nrhs);
+    T2 *y = BWD ? vptr<T2>(vb, tk.x, nrhs) : vptr<T2>(vb, tk.y, nrhs);  // output
+    const T2 *vv = vptr<T2>(vb, tk.v, nrhs);
+    const T2 *acc = (BWD && tk.acc >= 0) ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
+    for (int ot = 0; ot < t; ++ot) {
+        double2 s[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = make_double2(0, 0);
+        for (int it = 0; it < t; ++it) {
+            // forward: y[ot] += TT[ot, it] x[it];  backward: x[ot] += TT[it, ot]^T w[it]
+            const T2 *tile = BWD ? TT + ((int64_t)ot * t + it) * TILE_ELEMS_D : TT + ((int64_t)it * t + ot) * TILE_ELEMS_D;
+            __syncthreads();
+            for (int e = threadIdx.x; e < 4096; e += 256) Ls[(e >> 6) * 65 + (e & 63)] = tile[e];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = threadIdx.x + 256 * i;
                 const int r = e & 63, c = e >> 6;
-                double2 acc = make_double2(0, 0);
-                for (int ct = 0; ct < t; ++ct) {
-                    const T2 *tile = TT + ((int64_t)ct * t + bt) * TILE_ELEMS_D;
-                    const T2 *xs = x + ct * vt + c * 64;
-                    for (int q = 0; q < 64; ++q) acc = cadd(acc, cmul(to_d2(tile[q * 64 + r]), to_d2(xs[q])));
+                if (c < ncol) {
+                    double2 a = s[i];
+                    if (!BWD) {
+                        const T2 *xs = xin + it * vt + (int64_t)(c0 + c) * 64;
+                        for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[q * 65 + r]), to_d2(xs[q])));
+                    } else {
+                        const T2 *vs = vv + it * vt + (int64_t)(c0 + c) * 64;
+                        const T2 *as = acc ? acc + it * vt + (int64_t)(c0 + c) * 64 : nullptr;
+                        for (int q = 0; q < 64; ++q) {
+                            double2 w = to_d2(vs[q]);
+                            if (as) w = csub(w, to_d2(as[q]));
+                            a = cadd(a, cmul(to_d2(Ls[r * 65 + q]), w));
+                        }
+                    }
+                    s[i] = a;
                 }
-                y[bt * vt + e] = from_d2<T2>(acc);
             }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if ((e >> 6) < ncol) y[ot * vt + (int64_t)c0 * 64 + e] = from_d2<T2>(s[i]);
+        }
+    }
+    if (!BWD) {
         __syncthreads();
-        for (int64_t e = threadIdx.x; e < t * vt; e += blockDim.x) {
-            const int bt = (int)(e / vt);
-            const int rem = (int)(e - bt * vt);
-            const int r = rem & 63, c = rem >> 6;
-            const int row = bt * 64 + r;
+        T2 *v = vptr<T2>(vb, tk.v, nrhs);
+        for (int64_t e = threadIdx.x; e < (int64_t)t * 64 * ncol; e += blockDim.x) {
+            const int ot = (int)(e / (64 * ncol));
+            const int rem = (int)(e - (int64_t)ot * 64 * ncol);
+            const int r = rem & 63, c = c0 + (rem >> 6);
+            const int row = ot * 64 + r;
             const int64_t dr = tk.drow + row;
             double2 val = make_double2(0, 0);
             if (row < tk.n) {
-                val = cmul(D.dinv[dr], to_d2(y[e]));
+                val = cmul(D.dinv[dr], to_d2(y[ot * vt + (int64_t)c * 64 + r]));
                 const int pv = D.piv[dr];
                 if (pv != 0) {
                     const int pr = row + pv;
-                    val = cadd(val, cmul(D.dinvoff[dr], to_d2(y[(pr >> 6) * vt + c * 64 + (pr & 63)])));
+                    val = cadd(val, cmul(D.dinvoff[dr], to_d2(y[(pr >> 6) * vt + (int64_t)c * 64 + (pr & 63)])));
                 }
             }
-            v[e] = from_d2<T2>(val);
+            v[ot * vt + (int64_t)c * 64 + r] = from_d2<T2>(val);
         }
-    } else {
-        T2 *x = vptr<T2>(vb, tk.x, nrhs);
-        const T2 *v = vptr<T2>(vb, tk.v, nrhs);
-        const T2 *acc = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
-        for (int ct = 0; ct < t; ++ct)
-            for (int e = threadIdx.x; e < vt; e += blockDim.x) {
-                const int r = e & 63, c = e >> 6;
-                double2 s = make_double2(0, 0);
-                for (int bt = 0; bt < t; ++bt) {
-                    const T2 *tile = TT + ((int64_t)ct * t + bt) * TILE_ELEMS_D;
-                    const T2 *vs = v + bt * vt + c * 64;
-                    const T2 *as = acc ? acc + bt * vt + c * 64 : nullptr;
-                    for (int q = 0; q < 64; ++q) {
-                        double2 w = to_d2(vs[q]);
-                        if (as) w = csub(w, to_d2(as[q]));
-                        s = cadd(s, cmul(to_d2(tile[r * 64 + q]), w));
-                    }
-                }
-                x[ct * vt + e] = from_d2<T2>(s);
-            }
     }
 }
 
@@ -249,8 +263,9 @@ hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, bool bwd, const B
                         const DArrays &D, int nrhs, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
-    if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, b, vb, D, nrhs);
-    else hipLaunchKernelGGL((vdiag_kernel<T2, false>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
+    if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    else hipLaunchKernelGGL((vdiag_kernel<T2, false>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
     return hipGetLastError();
 }
 template <typename T>
