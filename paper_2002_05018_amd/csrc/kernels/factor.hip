@@ -288,255 +288,262 @@ __device__ __forceinline__ void wave_argmax_col(const double2 *col, int lo, int 
     mi = b ? (__ffsll((long long)b) - 1) : -1;
 }
 
+// c ? x : y on the components (a conditional on the vector class itself
+// selects between addresses and forces its operands into private memory)
+__device__ __forceinline__ double2 sel2(bool c, double2 x, double2 y) {
+    return make_double2(c ? x.x : y.x, c ? x.y : y.y);
+}
+// v if keep, else +0 (bitwise, so that no select of the register array is
+// turned into an indexed private-memory access)
+__device__ __forceinline__ double2 keep_or_zero(double2 v, bool keep) {
+    const long long m = -(long long)keep;
+    return make_double2(__longlong_as_double(__double_as_longlong(v.x) & m),
+                        __longlong_as_double(__double_as_longlong(v.y) & m));
+}
+
 // Bunch-Kaufman on a block of order <= 64 (same pivoting rule and outputs as
-// bk_kernel).  The block is a full symmetric square in registers: thread
-// (pr, qc) of a TR x TC grid owns rows pr + TR a and columns qc + TC b.  So is
-// Z = L^{-1}, accumulated alongside the elimination (Z <- (I - l_k e_k^T) Z,
-// with the row interchanges applied to Z as to L).  Each pivot step
-// publishes the pivot column (and column r, and the rows that move) through
-// small LDS vectors; every wave reduces them itself with DPP, so a step costs
-// two or three work-group barriers.
-template <typename T2, int TR, int TC>
-__global__ __launch_bounds__(TR * TC) void bk64_kernel(const BkTask *tasks, Bases bases, DArrays D, int *status) {
-    constexpr int NM = 64, NT = TR * TC, RA = NM / TR, RB = NM / TC;
-    __shared__ double2 colk[NM], colr[NM], rkk[NM], rp[NM], zk[NM], zkk[NM], zp[NM];
+// bk_kernel) with implicit interchanges.  The block stays in its stored
+// (physical) order: lane r of wave w (NW waves) holds, for the columns
+// s = w + NW b, A(r, s) and Z(s, r), Z = L^{-1} in physical order (TT(b, c)
+// = Z(perm b, c)).  An interchange only updates the permutation (held by
+// every wave, one entry per lane) and the mask of rows not yet eliminated.
+//
+// Each step is one work-group barrier.  Before it, the wave owning the next
+// natural pivot column p (logical position k) publishes through LDS the
+// column of A, with p and the eliminated rows zeroed, row p of Z, and the
+// start of the pivot test it computes itself: the largest remaining
+// off-diagonal magnitude, its row, and 1/A(p, p).  So the search is done
+// while the other waves still update, and after the barrier every wave reads
+// all operands of the common step (a 1x1 pivot that needs no interchange) in
+// one round of loads.  When the test needs column r, its owner publishes it
+// and a second barrier follows.  The update touches only the remaining
+// columns s:
+//   A(r, s) -= l(r) x(s),   Z(s, r) -= w(r) x(s),
+// with l = X(r, :) E^{-1} (zero on eliminated rows: masked column) and
+// w = Z(piv, r) E^{-1} (zero on remaining rows).  The pivot column of a 1x1
+// step keeps A(r, p), and L = A(r, p) / d is formed at the end; a 2x2 step
+// stores its multipliers directly.  Equal magnitudes in the pivot search go
+// to the lowest stored row.
+struct BkHead {
+    double2 dg, inv;  // pivot A(p, p) and its reciprocal
+    double lam;       // largest remaining off-diagonal magnitude in column p
+    int r;            // its row (lowest on ties), or p when there is none
+    int pad;
+};
+
+template <typename T2, int NW>
+__global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, Bases bases, DArrays D, int *status) {
+    constexpr int NM = 64, RB = NM / NW, SLD = NM + 1;
+    typedef double Regs __attribute__((ext_vector_type(2 * RB)));
+    __shared__ double2 colA[2][NM], zcA[2][NM], colB[2][NM], zcB[2][NM];
+    __shared__ BkHead head[2];
+    __shared__ double2 dgB[2];
     __shared__ double2 sd[NM], sdoff[NM], sdinv[NM], sdinvoff[NM];  // D outputs, flushed at the end
-    __shared__ int sperm[NM], spiv[NM];
+    __shared__ int spiv[NM];
+    __shared__ double2 stage[NM * SLD];  // TT staged for coalesced stores
 
     const BkTask tk = tasks[blockIdx.x];
-    const int n = tk.n, t = threadIdx.x, pr = t % TR, qc = t / TR;
-    double2 a[RA][RB], z[RA][RB];
+    const int n = tk.n, t = threadIdx.x;
+    const int lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const double2 zero = make_double2(0, 0);
+    // A(lane, s) and Z(s, lane) for s = w + NW b, as (re, im) pairs; a vector so
+    // that a column picked by a wave-uniform b is a register-indexed move
+    Regs av, zv;
     {
         const T2 *src = enc_ptr<T2>(bases, tk.a);
 #pragma unroll
-        for (int aa = 0; aa < RA; ++aa)
-#pragma unroll
-            for (int bb = 0; bb < RB; ++bb) {
-                const int i = pr + TR * aa, j = qc + TC * bb;
-                a[aa][bb] = make_double2(0, 0);
-                if (i < n && j < n) a[aa][bb] = to_d2(src[tile_elem(i > j ? i : j, i > j ? j : i, tk.ldt)]);
-                z[aa][bb] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-            }
+        for (int bb = 0; bb < RB; ++bb) {
+            const int i = lane, j = w + NW * bb;
+            double2 v = zero;
+            if (i < n && j < n) v = to_d2(src[tile_elem(i > j ? i : j, i > j ? j : i, tk.ldt)]);
+            av[2 * bb] = v.x;
+            av[2 * bb + 1] = v.y;
+            zv[2 * bb] = i == j ? 1.0 : 0.0;
+            zv[2 * bb + 1] = 0.0;
+        }
     }
-    if (t < NM) sperm[t] = t;
-    __syncthreads();
+    int vperm = lane, vinv = lane;  // perm[lane] and its inverse
+    unsigned long long active = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 
-    int k = 0;
+    // publish column p (owner wave) into buffer bf with the start of its test
+    auto publish = [&](int p, int bf, unsigned long long act) {
+        const int b = p / NW;
+        const double2 x = make_double2(av[2 * b], av[2 * b + 1]);
+        const bool keep = ((act >> lane) & 1ull) && lane != p;
+        colA[bf][lane] = keep_or_zero(x, keep);
+        zcA[bf][lane] = make_double2(zv[2 * b], zv[2 * b + 1]);
+        const double lv = keep ? cabs1(x) : -1.0;
+        const double lam = fmax(wave_max(lv), 0.0);
+        const unsigned long long cand = __ballot(keep && lv == lam);
+        const int r = cand ? __ffsll((long long)cand) - 1 : p;
+        if (lane == p) {
+            head[bf].dg = x;
+            head[bf].inv = crecip(x);
+            head[bf].lam = lam;
+            head[bf].r = r;
+        }
+    };
+    if (n > 0 && w == 0) publish(0, 0, active);
+
+    int k = 0, step = 0;
     bool singular = false;
     while (k < n) {
-        const int qk = k % TC, bk = k / TC;
-        if (qc == qk) {
-#pragma unroll
-            for (int bb = 0; bb < RB; ++bb)
-                if (bb == bk) {
-#pragma unroll
-                    for (int aa = 0; aa < RA; ++aa) colk[pr + TR * aa] = a[aa][bb];
-                }
-        }
+        const int buf = step & 1;
+        const int pk = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(vperm, k));
         __syncthreads();
-        double lam1;
-        int r;
-        wave_argmax_col(colk, k + 1, n, -1, lam1, r);
-        if (lam1 < 0.0 || r < 0) { lam1 = 0.0; r = k; }
-        const double akk = cabs1(colk[k]);
-        int size = 1, p = k;
+        // ---- operands of the common step, in one round of loads
+        const double2 dA = uni2(head[buf].dg);
+        double2 e11 = uni2(head[buf].inv);
+        const double lam1 = uni(head[buf].lam);
+        const int r = __builtin_amdgcn_readfirstlane(head[buf].r);
+        const double2 xl = colA[buf][lane], zl = zcA[buf][lane];
+        double2 xs[RB];
+#pragma unroll
+        for (int bb = 0; bb < RB; ++bb) xs[bb] = colA[buf][w + NW * bb];
+        const double akk = cabs1(dA);
+        int size = 1, p0 = pk, p1 = pk;
+        double2 dB = zero;
         if (!(fmax(akk, lam1) > 0.0)) {
             singular = true;
-        } else if (!(akk >= kAlphaBK * lam1) && r > k) {
-            const int qr = r % TC, br = r / TC;
-            if (qc == qr) {
-#pragma unroll
-                for (int bb = 0; bb < RB; ++bb)
-                    if (bb == br) {
-#pragma unroll
-                        for (int aa = 0; aa < RA; ++aa) colr[pr + TR * aa] = a[aa][bb];
-                    }
+        } else if (!(akk >= kAlphaBK * lam1) && r != pk) {
+            // ---- publish column r of A (remaining rows other than r) and row r of Z
+            if (w == r % NW) {
+                const int b = r / NW;
+                const double2 v = make_double2(av[2 * b], av[2 * b + 1]);
+                colB[buf][lane] = keep_or_zero(v, ((active >> lane) & 1ull) && lane != r);
+                zcB[buf][lane] = make_double2(zv[2 * b], zv[2 * b + 1]);
+                if (lane == r) dgB[buf] = v;
             }
             __syncthreads();
-            double sigma;
-            int dummy;
-            wave_argmax_col(colr, k, n, r, sigma, dummy);
-            const double arr = cabs1(colr[r]);
-            if (akk * sigma >= kAlphaBK * lam1 * lam1) { size = 1; p = k; }
-            else if (arr >= kAlphaBK * sigma) { size = 1; p = r; }
-            else { size = 2; p = r; }
+            const bool sact = ((active >> lane) & 1ull) && lane != r;
+            const double sv = sact ? cabs1(colB[buf][lane]) : -1.0;
+            const double sigma = fmax(wave_max(sv), 0.0);
+            dB = uni2(dgB[buf]);
+            const double arr = cabs1(dB);
+            if (akk * sigma >= kAlphaBK * lam1 * lam1) { size = 1; p0 = pk; }
+            else if (arr >= kAlphaBK * sigma) { size = 1; p0 = r; }
+            else { size = 2; p0 = pk; p1 = r; }
         }
         if (singular) break;
-        const int kk = k + size - 1;
-        const bool swap = p != kk;
-        // ---- publish the rows that move (rows kk, p of A and Z; row k of Z)
-        if (swap && pr == kk % TR) {
-            const int ak = kk / TR;
-#pragma unroll
-            for (int aa = 0; aa < RA; ++aa)
-                if (aa == ak) {
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) { rkk[qc + TC * bb] = a[aa][bb]; zkk[qc + TC * bb] = z[aa][bb]; }
-                }
+        if (size == 1) p1 = p0;
+        // ---- interchange: logical position q (k for a 1x1 pivot, k+1 for a
+        // 2x2 one) receives row r
+        if (p0 != pk || size == 2) {
+            const int q = k + size - 1;
+            const int posr = __builtin_amdgcn_readlane(vinv, r);
+            const int atq = __builtin_amdgcn_readlane(vperm, q);
+            if (lane == q) vperm = r;
+            if (lane == posr) vperm = atq;
+            if (lane == r) vinv = q;
+            if (lane == atq) vinv = posr;
         }
-        if ((swap || size == 2) && pr == p % TR) {
-            const int ap = p / TR;
+        const unsigned long long rest = active & ~((1ull << p0) | (1ull << p1));
+        const int pnext = k + size < n ? __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(vperm, k + size)) : -1;
+        // ---- pivot block E = [[ea, eb], [eb, ec]] and its inverse; per row the
+        // coefficients l_u, w_u of each pivot column u
+        double2 ea, eb = zero, ec = zero, e12 = zero, e22 = zero, l0, l1 = zero, w0, w1 = zero;
+        if (size == 1 && p0 == pk) {
+            ea = dA;
+            l0 = cmul(xl, e11);
+            w0 = cmul(zl, e11);
+        } else if (size == 1) {
+            ea = dB;
+            e11 = uni2(crecip(dB));
+            l0 = cmul(colB[buf][lane], e11);
+            w0 = cmul(zcB[buf][lane], e11);
 #pragma unroll
-            for (int aa = 0; aa < RA; ++aa)
-                if (aa == ap) {
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) { rp[qc + TC * bb] = a[aa][bb]; zp[qc + TC * bb] = z[aa][bb]; }
-                }
-        }
-        if ((size == 2 || !swap) && pr == k % TR) {
-            const int ak = k / TR;
-#pragma unroll
-            for (int aa = 0; aa < RA; ++aa)
-                if (aa == ak) {
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) zk[qc + TC * bb] = z[aa][bb];
-                }
-        }
-        __syncthreads();
-        auto pi = [&](int x) { return !swap ? x : (x == kk ? p : (x == p ? kk : x)); };
-        // ---- symmetric interchange kk <-> p (rows of A, L and Z; columns of A)
-        if (swap) {
-#pragma unroll
-            for (int aa = 0; aa < RA; ++aa) {
-                const int i = pr + TR * aa;
-                if (i == kk || i == p) {
-                    const double2 *src = (i == kk) ? rp : rkk;
-                    const double2 *zsrc = (i == kk) ? zp : zkk;
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) {
-                        const int j = qc + TC * bb;
-                        a[aa][bb] = src[pi(j)];
-                        if (j < k) z[aa][bb] = zsrc[j];
-                    }
-                }
-            }
-#pragma unroll
-            for (int bb = 0; bb < RB; ++bb) {
-                const int j = qc + TC * bb;
-                if (j == kk || j == p) {
-                    const double2 *src = (j == kk) ? rp : rkk;
-#pragma unroll
-                    for (int aa = 0; aa < RA; ++aa) {
-                        const int i = pr + TR * aa;
-                        if (i != kk && i != p) a[aa][bb] = src[i];
-                    }
-                }
-            }
-            if (t == 0) { int sw = sperm[kk]; sperm[kk] = sperm[p]; sperm[p] = sw; }
-        }
-        // ---- pivot block and multipliers.  New column k: c0[pi(.)] with
-        // c0 = row p for a 1x1 pivot with interchange, else column k; new
-        // column k+1 (2x2): row p [pi(.)].
-        const bool two = size == 2;
-        const double2 *c0 = (!two && swap) ? rp : colk;
-        const double2 ea = uni2(c0[pi(k)]);
-        double2 e11, e12, e22, eb = make_double2(0, 0), ec = make_double2(0, 0);
-        if (!two) {
-            e11 = uni2(crecip(ea));
-            e12 = e22 = make_double2(0, 0);
+            for (int bb = 0; bb < RB; ++bb) xs[bb] = colB[buf][w + NW * bb];
         } else {
-            eb = uni2(colk[p]);
-            ec = uni2(rp[p]);
+            ea = dA;
+            ec = dB;
+            eb = uni2(colA[buf][p1]);
             const double2 idet = crecip(csub(cmul(ea, ec), cmul(eb, eb)));
             e11 = uni2(cmul(ec, idet));
             e22 = uni2(cmul(ea, idet));
             e12 = uni2(make_double2(-(eb.x * idet.x - eb.y * idet.y), -(eb.x * idet.y + eb.y * idet.x)));
+            const bool rin = (rest >> lane) & 1ull;
+            const double2 u1 = colB[buf][lane], z1 = zcB[buf][lane];
+            l0 = keep_or_zero(cadd(cmul(xl, e11), cmul(u1, e12)), rin);
+            l1 = keep_or_zero(cadd(cmul(xl, e12), cmul(u1, e22)), rin);
+            w0 = cadd(cmul(zl, e11), cmul(z1, e12));
+            w1 = cadd(cmul(zl, e12), cmul(z1, e22));
         }
-        // column values of the owned columns and rows of Z'(k,.), Z'(k+1,.)
-        const double2 *z0row = (!two && swap) ? zp : zk;
-        double2 xc0[RB], xc1[RB], zr0[RB], zr1[RB];
+        // ---- rank-1 update per pivot column, remaining columns only
 #pragma unroll
         for (int bb = 0; bb < RB; ++bb) {
-            const int j = qc + TC * bb;
-            const bool trail = j > kk && j < n;
-            xc0[bb] = trail ? c0[pi(j)] : make_double2(0, 0);
-            xc1[bb] = (trail && two) ? rp[pi(j)] : make_double2(0, 0);
-            zr0[bb] = (j == k) ? make_double2(1.0, 0.0) : (j < k ? z0row[j] : make_double2(0, 0));
-            zr1[bb] = two ? ((j == k + 1) ? make_double2(1.0, 0.0) : (j < k ? zp[j] : make_double2(0, 0)))
-                          : make_double2(0, 0);
+            if ((rest >> (w + NW * bb)) & 1ull) {
+                const double2 v = cfma_neg(make_double2(av[2 * bb], av[2 * bb + 1]), l0, xs[bb]);
+                const double2 y = cfma_neg(make_double2(zv[2 * bb], zv[2 * bb + 1]), w0, xs[bb]);
+                av[2 * bb] = v.x; av[2 * bb + 1] = v.y;
+                zv[2 * bb] = y.x; zv[2 * bb + 1] = y.y;
+            }
         }
-        // ---- rank-1 / rank-2 update.  For a column j only one of A (trailing,
-        // j > kk) and Z (eliminated, j <= kk) changes; column groups bb are
-        // uniform except the one holding the pivot columns.
+        if (size == 2) {
 #pragma unroll
-        for (int aa = 0; aa < RA; ++aa) {
-            const int i = pr + TR * aa;
-            if (i > kk && i < n) {
-                const double2 x0 = c0[pi(i)];
-                if (!two) {
-                    const double2 l0 = cmul(x0, e11);
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) {
-                        const int j = qc + TC * bb;
-                        if (TC * bb > k) {
-                            a[aa][bb] = cfma_neg(a[aa][bb], l0, xc0[bb]);
-                        } else if (TC * bb + TC - 1 < k) {
-                            z[aa][bb] = cfma_neg(z[aa][bb], l0, zr0[bb]);
-                        } else {
-                            if (j > k) a[aa][bb] = cfma_neg(a[aa][bb], l0, xc0[bb]);
-                            else z[aa][bb] = cfma_neg(z[aa][bb], l0, zr0[bb]);
-                            if (j == k) a[aa][bb] = l0;
-                        }
-                    }
-                } else {
-                    const double2 x1 = rp[pi(i)];
-                    const double2 l0 = cadd(cmul(x0, e11), cmul(x1, e12));
-                    const double2 l1 = cadd(cmul(x0, e12), cmul(x1, e22));
-#pragma unroll
-                    for (int bb = 0; bb < RB; ++bb) {
-                        const int j = qc + TC * bb;
-                        if (TC * bb > kk) {
-                            a[aa][bb] = cfma_neg(cfma_neg(a[aa][bb], l0, xc0[bb]), l1, xc1[bb]);
-                        } else if (TC * bb + TC - 1 < k) {
-                            z[aa][bb] = cfma_neg(cfma_neg(z[aa][bb], l0, zr0[bb]), l1, zr1[bb]);
-                        } else {
-                            if (j > kk) a[aa][bb] = cfma_neg(cfma_neg(a[aa][bb], l0, xc0[bb]), l1, xc1[bb]);
-                            else z[aa][bb] = cfma_neg(cfma_neg(z[aa][bb], l0, zr0[bb]), l1, zr1[bb]);
-                            if (j == k) a[aa][bb] = l0;
-                            if (j == k + 1) a[aa][bb] = l1;
-                        }
-                    }
+            for (int bb = 0; bb < RB; ++bb) {
+                const int sc = w + NW * bb;
+                const double2 x1 = colB[buf][sc];
+                if ((rest >> sc) & 1ull) {
+                    const double2 v = cfma_neg(make_double2(av[2 * bb], av[2 * bb + 1]), l1, x1);
+                    const double2 y = cfma_neg(make_double2(zv[2 * bb], zv[2 * bb + 1]), w1, x1);
+                    av[2 * bb] = v.x; av[2 * bb + 1] = v.y;
+                    zv[2 * bb] = y.x; zv[2 * bb + 1] = y.y;
                 }
             }
-            if (two && i == k + 1) {
-#pragma unroll
-                for (int bb = 0; bb < RB; ++bb)
-                    if (qc + TC * bb == k) a[aa][bb] = make_double2(0, 0);
+            // a 2x2 step stores its multipliers; L(k+1, k) = 0
+            const bool rin = (rest >> lane) & 1ull;
+            if (w == p0 % NW) {
+                const int b = p0 / NW;
+                const double2 v = sel2(rin, l0, sel2(lane == p1, zero, make_double2(av[2 * b], av[2 * b + 1])));
+                av[2 * b] = v.x; av[2 * b + 1] = v.y;
+            }
+            if (w == p1 % NW) {
+                const int b = p1 / NW;
+                const double2 v = sel2(rin, l1, make_double2(av[2 * b], av[2 * b + 1]));
+                av[2 * b] = v.x; av[2 * b + 1] = v.y;
             }
         }
+        // ---- the next pivot column's owner publishes it and starts its test
+        if (pnext >= 0 && w == pnext % NW) publish(pnext, buf ^ 1, rest);
         if (t == 0) {
-            sd[k] = ea; sdoff[k] = eb; sdinv[k] = e11; sdinvoff[k] = e12; spiv[k] = two ? 1 : 0;
-            if (two) { sd[k + 1] = ec; sdoff[k + 1] = eb; sdinv[k + 1] = e22; sdinvoff[k + 1] = e12; spiv[k + 1] = -1; }
+            sd[k] = ea; sdoff[k] = eb; sdinv[k] = e11; sdinvoff[k] = e12; spiv[k] = size == 2 ? 1 : 0;
+            if (size == 2) { sd[k + 1] = ec; sdoff[k + 1] = eb; sdinv[k + 1] = e22; sdinvoff[k + 1] = e12; spiv[k + 1] = -1; }
         }
-        __syncthreads();
+        active = rest;
         k += size;
+        ++step;
     }
     if (singular) {
         if (t == 0) status[tk.status] = k + 1;
         return;
     }
+    __syncthreads();
     const int64_t dr = tk.drow;
     if (t < n) {
         D.d[dr + t] = sd[t]; D.doff[dr + t] = sdoff[t];
         D.dinv[dr + t] = sdinv[t]; D.dinvoff[dr + t] = sdinvoff[t];
         D.piv[dr + t] = spiv[t];
-        D.perm[dr + t] = sperm[t];
+        D.perm[dr + t] = vperm;
     }
-    // ---- outputs: unit lower L and TT = Z P^T (zero elsewhere in the tile)
+    // ---- outputs: unit lower L(a, b) = A(perm a, perm b) (times 1/d for a
+    // 1x1 pivot column); TT(inv s, c) = Z(s, c), zero outside the n x n corner
     T2 *lout = enc_ptr<T2>(bases, tk.l);
     T2 *tt = enc_ptr<T2>(bases, tk.tt);
+    const int la = vinv;
 #pragma unroll
-    for (int aa = 0; aa < RA; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < RB; ++bb) {
-            const int i = pr + TR * aa, j = qc + TC * bb;
-            if (i < n && j < n && i >= j)
-                lout[tile_elem(i, j, tk.ldt)] = from_d2<T2>(i == j ? make_double2(1.0, 0.0) : a[aa][bb]);
-            // TT[i][perm[j]] = Z[i][j]; columns perm[j] for j >= n are padding
-            const int col = j < n ? sperm[j] : j;
-            const double2 zv = (i < n && j < n && i >= j) ? z[aa][bb] : make_double2(0, 0);
-            tt[col * 64 + i] = from_d2<T2>(zv);
+    for (int bb = 0; bb < RB; ++bb) {
+        const int sc = w + NW * bb;
+        const int lb = __builtin_amdgcn_readlane(vinv, sc);
+        const bool in = lane < n && sc < n;
+        if (in && la >= lb) {
+            double2 v = make_double2(av[2 * bb], av[2 * bb + 1]);
+            if (spiv[lb] == 0) v = cmul(v, sdinv[lb]);
+            lout[tile_elem(la, lb, tk.ldt)] = from_d2<T2>(sel2(la == lb, make_double2(1.0, 0.0), v));
         }
+        stage[lane * SLD + lb] = sel2(in, make_double2(zv[2 * bb], zv[2 * bb + 1]), zero);
+    }
+    __syncthreads();
+    for (int e = t; e < NM * NM; e += 64 * NW) tt[e] = from_d2<T2>(stage[(e >> 6) * SLD + (e & 63)]);
 }
 
 // ------------------------------------------------- complex GEMM (MFMA) --
@@ -697,9 +704,8 @@ size_t bk_lds_bytes(int n, int nthr, bool lds) {
     return (a + 2 * (size_t)nthr) * sizeof(double2) + 16 * sizeof(double) + 16 * sizeof(int) + (size_t)nthr * sizeof(int);
 }
 
-#ifndef BK64_TR
-#define BK64_TR 32  // 32 x 16 threads: 8 elements of A and of Z per thread
-#define BK64_TC 16
+#ifndef BK64_NW
+#define BK64_NW 8  // 8 waves: 8 elements of A and of Z per thread
 #endif
 template <typename T>
 hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &b, const DArrays &D, int *status,
@@ -707,7 +713,7 @@ hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
     if (maxn <= 64) {
-        hipLaunchKernelGGL((bk64_kernel<T2, BK64_TR, BK64_TC>), dim3((unsigned)ntask), dim3(BK64_TR * BK64_TC), 0, s,
+        hipLaunchKernelGGL((bk64_kernel<T2, BK64_NW>), dim3((unsigned)ntask), dim3(64 * BK64_NW), 0, s,
                            tasks, b, D, status);
         return hipGetLastError();
     }
