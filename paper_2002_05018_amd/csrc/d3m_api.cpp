@@ -374,7 +374,7 @@ template <typename T>
 int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases &vb, bool bwd, int nrhs,
                hipStream_t s) {
     if (st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
-    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, bwd, b, vb, h->D, nrhs, s));
+    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, s));
     if (!st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
     return D3M_OK;
 }

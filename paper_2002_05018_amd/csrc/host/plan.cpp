@@ -422,6 +422,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
             t.acc = -1;
             t.drow = pl.drow_k[j];
             t.t = pl.kt[j]; t.n = nsz[j];
+            st.dg_maxt = std::max(st.dg_maxt, (int)t.t);
             pl.vdiag.push_back(t);
         }
         st.ndg = (i64)pl.vdiag.size() - st.dg0;
@@ -461,6 +462,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
             t.acc = V(V_KACC, pl.vk[j]);
             t.drow = pl.drow_k[j];
             t.t = pl.kt[j]; t.n = nsz[j];
+            st.dg_maxt = std::max(st.dg_maxt, (int)t.t);
             pl.vdiag.push_back(t);
         }
         st.ndg = (i64)pl.vdiag.size() - st.dg0;

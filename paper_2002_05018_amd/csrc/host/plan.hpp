@@ -24,6 +24,7 @@ struct FactorStep {
 // One sweep step of the solve: a diagonal launch and an update launch.
 struct SolveStep {
     i64 dg0 = 0, ndg = 0;
+    int dg_maxt = 1;  // largest number of tiles of a diagonal block in this step
     i64 up0 = 0, nup = 0;
     int up_mode = 0;  // 0: out -= sum L y   1: out = sum L^T x   2: out += sum L^T x
     bool up_first = false;  // run the update launch before the diagonal launch

@@ -39,7 +39,7 @@ template <typename T>
 hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t nrows, int nrhs, int64_t ne,
                          hipStream_t s);
 template <typename T>
-hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, bool bwd, const Bases &b, const VBases &vb,
+hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
                         const DArrays &D, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pairs, int mode, const Bases &b,

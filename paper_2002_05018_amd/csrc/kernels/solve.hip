@@ -2,6 +2,8 @@
 // refinement / adjoint helpers.  Vector tiles hold 64 rows x nrhs columns,
 // column-major (one right-hand side after another), so one 64 x 64 factor
 // tile is applied to every right-hand side while it sits in LDS.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -28,13 +30,183 @@ __global__ void vsplit_kernel(T2 *X, const double2 *f, const int64_t *map, int64
     X[idx] = e >= 0 ? from_d2<T2>(f[(int64_t)c * ne + e]) : T2{0, 0};
 }
 
+// Tile products of the solve sweeps: out (64 x ncol, ncol <= 8 right-hand
+// sides per block) gets op(L) X for 64 x 64 factor tiles L, op = identity
+// or transpose.  Lane r of wave w (4 waves) accumulates row r over the
+// inner indices q in [16 w, 16 w + 16); the four partial sums are added in
+// a fixed order through LDS (results do not depend on timing).  For op =
+// identity each lane reads its 16 entries of L straight from memory (one
+// 1 KB row of lanes per load); for the transpose the tile is staged through
+// LDS (row stride 65) first.  The X block is staged through LDS and read
+// as a broadcast.
+constexpr int SV_COLS = 8;
+
+template <typename T2, bool TR> struct SolveSmem {
+    double2 ls[TR ? 64 * 65 : 4 * SV_COLS * 64];  // staged tile; reused for the partial sums
+    double2 xs[SV_COLS * 64];                     // X(q, c) at c * 64 + q
+};
+
+// this thread's 16 entries op(L)(r, q), q = 16 w + j
+template <typename T2, bool TR>
+__device__ __forceinline__ void load_ltile(double (&lx)[16], double (&ly)[16], const T2 *tile, double2 *ls) {
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (!TR) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const T2 v = tile[(16 * w + j) * 64 + r];
+            lx[j] = v.x;
+            ly[j] = v.y;
+        }
+    } else {
+        // stage: element e of the column-major tile is L(e & 63, e >> 6)
+        T2 v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = tile[threadIdx.x + 256 * i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            ls[(e >> 6) * 65 + (e & 63)] = to_d2(v[i]);
+        }
+        __syncthreads();
+        // L^T(r, q) = L(q, r) at ls[r * 65 + q]
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double2 u = ls[r * 65 + 16 * w + j];
+            lx[j] = u.x;
+            ly[j] = u.y;
+        }
+    }
+}
+
+// X block (columns c0 .. c0 + ncol - 1 of a vector tile, minus sub) into xs
+template <typename T2>
+__device__ __forceinline__ void stage_x(double2 *xs, const T2 *src, const T2 *sub, int c0, int ncol) {
+    double2 v[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        v[i] = make_double2(0, 0);
+        if (e < 64 * ncol) {
+            v[i] = to_d2(src[(int64_t)c0 * 64 + e]);
+            if (sub) v[i] = csub(v[i], to_d2(sub[(int64_t)c0 * 64 + e]));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < 64 * ncol) xs[e] = v[i];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_fma(double (&ax)[SV_COLS], double (&ay)[SV_COLS], const double (&lx)[16],
+                                         const double (&ly)[16], const double2 *xs, int ncol) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int q = 16 * w + j;
+#pragma unroll
+        for (int c = 0; c < SV_COLS; ++c) {
+            if (c < ncol) {
+                const double2 x = xs[c * 64 + q];
+                ax[c] = fma(lx[j], x.x, fma(-ly[j], x.y, ax[c]));
+                ay[c] = fma(lx[j], x.y, fma(ly[j], x.x, ay[c]));
+            }
+        }
+    }
+}
+
+// sum of the four waves' partials for (row r, column c) in a fixed order;
+// thread (r, w) finishes columns w and w + 4
+__device__ __forceinline__ void reduce_partials(double2 *red, const double (&ax)[SV_COLS], const double (&ay)[SV_COLS],
+                                                double2 (&res)[2]) {
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < SV_COLS; ++c) red[(w * SV_COLS + c) * 64 + r] = make_double2(ax[c], ay[c]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = w + 4 * h;
+        double2 s = red[(0 * SV_COLS + c) * 64 + r];
+        s = cadd(s, red[(1 * SV_COLS + c) * 64 + r]);
+        s = cadd(s, red[(2 * SV_COLS + c) * 64 + r]);
+        s = cadd(s, red[(3 * SV_COLS + c) * 64 + r]);
+        res[h] = s;
+    }
+}
+
 // Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y.
 // Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
-// Each TT tile is staged through LDS (row stride 65) and applied to up to 32
-// right-hand sides (blockIdx.y selects the column chunk).
+// Blocks of one tile (n <= 64); blockIdx.y selects 8 right-hand sides.
 template <typename T2, bool BWD>
 __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
-    __shared__ T2 Ls[64 * 65];
+    __shared__ SolveSmem<T2, BWD> sm;
+    const VDiagTask tk = tasks[blockIdx.x];
+    const int c0 = blockIdx.y * SV_COLS;
+    const int ncol = min(SV_COLS, nrhs - c0);
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const T2 *TT = enc_ptr<T2>(b, tk.tt);
+    double lx[16], ly[16], ax[SV_COLS], ay[SV_COLS];
+#pragma unroll
+    for (int c = 0; c < SV_COLS; ++c) ax[c] = ay[c] = 0.0;
+    load_ltile<T2, BWD>(lx, ly, TT, sm.ls);
+    if (BWD) {
+        const T2 *accv = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
+        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.v, nrhs), accv, c0, ncol);
+    } else {
+        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
+    }
+    tile_fma(ax, ay, lx, ly, sm.xs, ncol);
+    double2 res[2];
+    reduce_partials(sm.ls, ax, ay, res);
+    if (BWD) {
+        T2 *x = vptr<T2>(vb, tk.x, nrhs);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = w + 4 * h;
+            if (c < ncol) x[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(res[h]);
+        }
+        return;
+    }
+    // v = D^{-1} y within the tile (2x2 pivots never cross it); y goes through xs
+    T2 *y = vptr<T2>(vb, tk.y, nrhs);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = w + 4 * h;
+        if (c < ncol) {
+            sm.xs[c * 64 + r] = res[h];
+            y[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(res[h]);
+        }
+    }
+    __syncthreads();
+    T2 *v = vptr<T2>(vb, tk.v, nrhs);
+    const int64_t dr = tk.drow + r;
+    const bool live = r < tk.n;
+    const double2 di = live ? D.dinv[dr] : make_double2(0, 0);
+    const int pv = live ? D.piv[dr] : 0;
+    const double2 dio = pv ? D.dinvoff[dr] : make_double2(0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = w + 4 * h;
+        if (c < ncol) {
+            double2 val = cmul(di, sm.xs[c * 64 + r]);
+            if (pv != 0) val = cadd(val, cmul(dio, sm.xs[c * 64 + r + pv]));
+            v[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(live ? val : make_double2(0, 0));
+        }
+    }
+}
+
+// Diagonal blocks of several tiles (blocks larger than 64 factored whole):
+// one work-group per block, 32 right-hand sides per blockIdx.y, each thread
+// one output at a time.
+template <typename T2, bool BWD>
+__global__ __launch_bounds__(256) void vdiag_multi_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D,
+                                                          int nrhs) {
+    __shared__ double2 Ls[64 * 65];
     const VDiagTask tk = tasks[blockIdx.x];
     const int t = tk.t;
     const T2 *TT = enc_ptr<T2>(b, tk.tt);
@@ -44,7 +216,7 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Base
     const T2 *xin = BWD ? nullptr : vptr<T2>(vb, tk.x, nrhs);
     T2 *y = BWD ? vptr<T2>(vb, tk.x, nrhs) : vptr<T2>(vb, tk.y, nrhs);  // output
     const T2 *vv = vptr<T2>(vb, tk.v, nrhs);
-    const T2 *acc = (BWD && tk.acc >= 0) ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
+    const T2 *accv = (BWD && tk.acc >= 0) ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
     for (int ot = 0; ot < t; ++ot) {
         double2 s[8];
 #pragma unroll
@@ -52,8 +224,15 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Base
         for (int it = 0; it < t; ++it) {
             // forward: y[ot] += TT[ot, it] x[it];  backward: x[ot] += TT[it, ot]^T w[it]
             const T2 *tile = BWD ? TT + ((int64_t)ot * t + it) * TILE_ELEMS_D : TT + ((int64_t)it * t + ot) * TILE_ELEMS_D;
+            T2 v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = tile[threadIdx.x + 256 * i];
             __syncthreads();
-            for (int e = threadIdx.x; e < 4096; e += 256) Ls[(e >> 6) * 65 + (e & 63)] = tile[e];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int e = threadIdx.x + 256 * i;
+                Ls[(e >> 6) * 65 + (e & 63)] = to_d2(v[i]);
+            }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -63,14 +242,14 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Base
                     double2 a = s[i];
                     if (!BWD) {
                         const T2 *xs = xin + it * vt + (int64_t)(c0 + c) * 64;
-                        for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[q * 65 + r]), to_d2(xs[q])));
+                        for (int q = 0; q < 64; ++q) a = cadd(a, cmul(Ls[q * 65 + r], to_d2(xs[q])));
                     } else {
                         const T2 *vs = vv + it * vt + (int64_t)(c0 + c) * 64;
-                        const T2 *as = acc ? acc + it * vt + (int64_t)(c0 + c) * 64 : nullptr;
+                        const T2 *as = accv ? accv + it * vt + (int64_t)(c0 + c) * 64 : nullptr;
                         for (int q = 0; q < 64; ++q) {
-                            double2 w = to_d2(vs[q]);
-                            if (as) w = csub(w, to_d2(as[q]));
-                            a = cadd(a, cmul(to_d2(Ls[r * 65 + q]), w));
+                            double2 wv = to_d2(vs[q]);
+                            if (as) wv = csub(wv, to_d2(as[q]));
+                            a = cadd(a, cmul(Ls[r * 65 + q], wv));
                         }
                     }
                     s[i] = a;
@@ -89,68 +268,55 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Base
         for (int64_t e = threadIdx.x; e < (int64_t)t * 64 * ncol; e += blockDim.x) {
             const int ot = (int)(e / (64 * ncol));
             const int rem = (int)(e - (int64_t)ot * 64 * ncol);
-            const int r = rem & 63, c = c0 + (rem >> 6);
-            const int row = ot * 64 + r;
+            const int rr = rem & 63, c = c0 + (rem >> 6);
+            const int row = ot * 64 + rr;
             const int64_t dr = tk.drow + row;
             double2 val = make_double2(0, 0);
             if (row < tk.n) {
-                val = cmul(D.dinv[dr], to_d2(y[ot * vt + (int64_t)c * 64 + r]));
+                val = cmul(D.dinv[dr], to_d2(y[ot * vt + (int64_t)c * 64 + rr]));
                 const int pv = D.piv[dr];
                 if (pv != 0) {
                     const int pr = row + pv;
                     val = cadd(val, cmul(D.dinvoff[dr], to_d2(y[(pr >> 6) * vt + (int64_t)c * 64 + (pr & 63)])));
                 }
             }
-            v[ot * vt + (int64_t)c * 64 + r] = from_d2<T2>(val);
+            v[ot * vt + (int64_t)c * 64 + rr] = from_d2<T2>(val);
         }
     }
 }
 
 // out (-=|=|+=) sum_p op(L_p) src_p with op = identity (mode 0) or
-// transpose (modes 1, 2); the factor tile is staged through LDS.
+// transpose (modes 1, 2); blockIdx.y selects 8 right-hand sides.
 template <typename T2, int MODE>
 __global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const VUpdPair *pairs, Bases b, VBases vb,
                                                    int nrhs) {
-    __shared__ T2 Ls[64 * 65];
+    constexpr bool TR = MODE != 0;
+    __shared__ SolveSmem<T2, TR> sm;
     const VUpdTask tk = tasks[blockIdx.x];
-    const int c0 = blockIdx.y * 32;
-    const int ncol = min(32, nrhs - c0);
-    T2 *out = vptr<T2>(vb, tk.out, nrhs);
-    double2 acc[8];
+    const int c0 = blockIdx.y * SV_COLS;
+    const int ncol = min(SV_COLS, nrhs - c0);
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double ax[SV_COLS], ay[SV_COLS];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = make_double2(0, 0);
+    for (int c = 0; c < SV_COLS; ++c) ax[c] = ay[c] = 0.0;
     for (int p = 0; p < tk.np; ++p) {
         const VUpdPair pr = pairs[tk.p0 + p];
-        const T2 *L = enc_ptr<T2>(b, pr.l);
-        const T2 *src = vptr<T2>(vb, pr.src, nrhs);
-        __syncthreads();
-        for (int e = threadIdx.x; e < 4096; e += 256) Ls[(e >> 6) * 65 + (e & 63)] = L[e];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            const int r = e & 63, c = e >> 6;
-            if (c < ncol) {
-                const T2 *s = src + (int64_t)(c0 + c) * 64;
-                double2 a = acc[i];
-                if (MODE == 0) {
-                    for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[q * 65 + r]), to_d2(s[q])));
-                } else {
-                    for (int q = 0; q < 64; ++q) a = cadd(a, cmul(to_d2(Ls[r * 65 + q]), to_d2(s[q])));
-                }
-                acc[i] = a;
-            }
-        }
+        double lx[16], ly[16];
+        load_ltile<T2, TR>(lx, ly, enc_ptr<T2>(b, pr.l), sm.ls);
+        stage_x<T2>(sm.xs, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
+        tile_fma(ax, ay, lx, ly, sm.xs, ncol);
     }
+    double2 res[2];
+    reduce_partials(sm.ls, ax, ay, res);
+    T2 *out = vptr<T2>(vb, tk.out, nrhs);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int e = threadIdx.x + 256 * i;
-        const int c = e >> 6;
+    for (int h = 0; h < 2; ++h) {
+        const int c = w + 4 * h;
         if (c < ncol) {
-            T2 *o = out + (int64_t)c0 * 64 + e;
-            if (MODE == 0) *o = from_d2<T2>(csub(to_d2(*o), acc[i]));
-            else if (MODE == 1) *o = from_d2<T2>(acc[i]);
-            else *o = from_d2<T2>(cadd(to_d2(*o), acc[i]));
+            T2 *o = out + (int64_t)(c0 + c) * 64 + r;
+            if (MODE == 0) *o = from_d2<T2>(csub(to_d2(*o), res[h]));
+            else if (MODE == 1) *o = from_d2<T2>(res[h]);
+            else *o = from_d2<T2>(cadd(to_d2(*o), res[h]));
         }
     }
 }
@@ -259,13 +425,19 @@ hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t 
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, bool bwd, const Bases &b, const VBases &vb,
+hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
                         const DArrays &D, int nrhs, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
-    dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
-    if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
-    else hipLaunchKernelGGL((vdiag_kernel<T2, false>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    if (maxt <= 1) {
+        dim3 grid((unsigned)ntask, (unsigned)((nrhs + SV_COLS - 1) / SV_COLS));
+        if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+        else hipLaunchKernelGGL((vdiag_kernel<T2, false>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    } else {
+        dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
+        if (bwd) hipLaunchKernelGGL((vdiag_multi_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+        else hipLaunchKernelGGL((vdiag_multi_kernel<T2, false>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+    }
     return hipGetLastError();
 }
 template <typename T>
@@ -273,7 +445,7 @@ hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pai
                        const VBases &vb, int nrhs, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
-    dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
+    dim3 grid((unsigned)ntask, (unsigned)((nrhs + SV_COLS - 1) / SV_COLS));
     if (mode == 0) hipLaunchKernelGGL((vupd_kernel<T2, 0>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
     else if (mode == 1) hipLaunchKernelGGL((vupd_kernel<T2, 1>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
     else hipLaunchKernelGGL((vupd_kernel<T2, 2>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
@@ -331,7 +503,7 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
 #define D3M_INST(T)                                                                                               \
     template hipError_t launch_vsplit<T>(void *, const double2 *, const int64_t *, int64_t, int, int64_t,          \
                                          hipStream_t);                                                            \
-    template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, bool, const Bases &, const VBases &,           \
+    template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, int, bool, const Bases &, const VBases &,           \
                                         const DArrays &, int, hipStream_t);                                       \
     template hipError_t launch_vupd<T>(const VUpdTask *, int64_t, const VUpdPair *, int, const Bases &,            \
                                        const VBases &, int, hipStream_t);                                         \
