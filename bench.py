@@ -33,7 +33,40 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-subdomains", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB three times (scale for HBM counters)")
     return ap.parse_args()
+
+
+def measured_traffic(config):
+    """HBM bytes per launch of the update GEMM from the committed counter
+    record, while the GEMM source is the one those counters were taken on."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "gemm_nt_update_config2_traffic.json")
+    src_path = os.path.join(ROOT, "paper_2002_05018_amd", "csrc", "kernels", "factor.hip")
+    if config != 2 or not os.path.exists(rec_path):
+        return None
+    src = open(src_path).read()
+    a = src.find("// ------------------------------------------------- complex GEMM (MFMA) --")
+    b = src.find("// ------------------------------------------------- L-hat = X D^{-1} -----")
+    if a < 0 or b < 0:
+        return None
+    rec = json.load(open(rec_path))
+    if hashlib.sha256(src[a:b].encode()).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 256 * 2 ** 20 // 16
+    x = torch.ones(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 16, "copies": 3}))
 
 
 def timed_steps(solver, precision, f, E, steps, warmup, torch):
@@ -97,6 +130,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "layout of this path is a design note, not a runnable configuration", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
 
@@ -142,7 +178,8 @@ def main():
                    "nrhs": prob.nrhs, "precision": "fp64"},
         "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel<double,1> (Schur updates)",
                      "achieved": achieved, "peak": MFMA_PEAK["c128"], "unit": "TFLOP/s",
-                     "frac": achieved / MFMA_PEAK["c128"], "traffic": None,
+                     "frac": achieved / MFMA_PEAK["c128"], "traffic": measured_traffic(args.config),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launches_per_step": n_launch,
                      "avg_launch_ms": up["total_ms"] / max(up["launches"], 1),
                      "flops_per_step": up["flops"] / max(args.steps, 1)},

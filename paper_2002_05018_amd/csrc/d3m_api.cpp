@@ -315,16 +315,22 @@ VBases vbases_of(d3m_problem *h) {
 template <typename T>
 int run_factor_step(d3m_problem *h, const FactorStep &st, const Bases &b, hipStream_t s) {
     hipEvent_t ev{};
-    h->prof_begin(ev, s);
-    HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
-    h->prof_end(KID_BK, ev, 0.0, s);
-    h->prof_begin(ev, s);
-    HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
-    HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
-    h->prof_end(KID_PANEL, ev, st.pan_flops, s);
-    h->prof_begin(ev, s);
-    HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.nup, h->d_pairs, b, 1, s));
-    h->prof_end(KID_UPDATE, ev, st.up_flops, s);
+    if (st.nbk > 0) {
+        h->prof_begin(ev, s);
+        HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
+        h->prof_end(KID_BK, ev, 0.0, s);
+    }
+    if (st.npan > 0 || st.nsc > 0) {
+        h->prof_begin(ev, s);
+        HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+        HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+        h->prof_end(KID_PANEL, ev, st.pan_flops, s);
+    }
+    if (st.nup > 0) {  // timed only when launched, so averages are per launch
+        h->prof_begin(ev, s);
+        HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.nup, h->d_pairs, b, 1, s));
+        h->prof_end(KID_UPDATE, ev, st.up_flops, s);
+    }
     return D3M_OK;
 }
 
