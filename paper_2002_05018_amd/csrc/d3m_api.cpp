@@ -90,6 +90,16 @@ struct d3m_problem {
     int64_t kstat_n[KID_COUNT] = {0};
     double kstat_flops[KID_COUNT] = {0};
     std::vector<hipEvent_t> ev_pool;
+    // second stream for the updates that the next elimination step does not
+    // need (look-ahead), and ordering events between the two streams
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> sync_pool;
+    size_t sync_next = 0;
+    hipEvent_t sync_event() {
+        hipEvent_t e = sync_pool[sync_next];
+        sync_next = (sync_next + 1) % sync_pool.size();
+        return e;
+    }
     struct Rec { int kid; hipEvent_t a, b; double flops; };
     std::vector<Rec> recs;
     size_t ev_next = 0;
@@ -103,6 +113,8 @@ struct d3m_problem {
         for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &norms})
             if (b->p) (void)hipFree(b->p);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
+        for (auto e : sync_pool) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 
     template <typename P>
@@ -206,6 +218,10 @@ int setup_device(d3m_problem *h) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(D3M_ENODEV, "no HIP device");
     if (h->opt.device < 0 || h->opt.device >= ndev) return fail(D3M_ENODEV, "device ordinal out of range");
     HIPCHK(hipSetDevice(h->opt.device));
+    // default priority (the same as the caller's streams)
+    HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    h->sync_pool.resize(512);
+    for (auto &e : h->sync_pool) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     Plan &pl = h->pl;
     int rc;
 #define UP(dst, vec) if ((rc = h->upload(dst, vec.data(), vec.size() * sizeof(vec[0]))) != D3M_OK) return rc
@@ -312,25 +328,52 @@ VBases vbases_of(d3m_problem *h) {
     return b;
 }
 
+// One elimination sweep (subdomain tiles or levels of K) with a look-ahead
+// of one step: the update tasks of step j that target the block columns of
+// step j + 1 (the first ncrit) run on the caller's stream right after the
+// panels; the others run on the side stream, overlapping the factorisation
+// of step j + 1.  Two launches never write the same tile at once: the
+// next-column updates of step j wait for the side-stream updates of step
+// j - 1 (which also reach those columns), and a side-stream launch starts
+// only after the panels it reads are scaled.
 template <typename T>
-int run_factor_step(d3m_problem *h, const FactorStep &st, const Bases &b, hipStream_t s) {
-    hipEvent_t ev{};
-    if (st.nbk > 0) {
-        h->prof_begin(ev, s);
-        HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
-        h->prof_end(KID_BK, ev, 0.0, s);
+int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
+    hipStream_t s2 = h->side;
+    hipEvent_t rest_done = nullptr;
+    for (const auto &st : steps) {
+        hipEvent_t ev{};
+        if (st.nbk > 0) {
+            h->prof_begin(ev, s);
+            HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
+            h->prof_end(KID_BK, ev, 0.0, s);
+        }
+        if (st.npan > 0 || st.nsc > 0) {
+            h->prof_begin(ev, s);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+            HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+            h->prof_end(KID_PANEL, ev, st.pan_flops, s);
+        }
+        const i64 nrest = st.nup - st.ncrit;
+        if (nrest > 0) {
+            hipEvent_t scaled = h->sync_event();
+            HIPCHK(hipEventRecord(scaled, s));
+            HIPCHK(hipStreamWaitEvent(s2, scaled, 0));
+            h->prof_begin(ev, s2);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + st.ncrit, nrest, h->d_pairs, b, 1, s2));
+            h->prof_end(KID_UPDATE, ev, st.up_flops - st.crit_flops, s2);
+        }
+        if (rest_done) HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
+        if (st.ncrit > 0) {  // timed only when launched, so averages are per launch
+            h->prof_begin(ev, s);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.ncrit, h->d_pairs, b, 1, s));
+            h->prof_end(KID_UPDATE, ev, st.crit_flops, s);
+        }
+        if (nrest > 0) {
+            rest_done = h->sync_event();
+            HIPCHK(hipEventRecord(rest_done, s2));
+        }
     }
-    if (st.npan > 0 || st.nsc > 0) {
-        h->prof_begin(ev, s);
-        HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
-        HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
-        h->prof_end(KID_PANEL, ev, st.pan_flops, s);
-    }
-    if (st.nup > 0) {  // timed only when launched, so averages are per launch
-        h->prof_begin(ev, s);
-        HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.nup, h->d_pairs, b, 1, s));
-        h->prof_end(KID_UPDATE, ev, st.up_flops, s);
-    }
+    if (rest_done) HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
     return D3M_OK;
 }
 
@@ -346,13 +389,11 @@ int factor_impl(d3m_problem *h, hipStream_t s) {
     HIPCHK(launch_coo_scatter<T>(b.p[ARR_M], h->d_coo_off, h->d_coo_val, (int64_t)pl.coo_off.size(), s));
     HIPCHK(hipMemsetAsync(h->d_status, 0, sizeof(int) * (pl.n_status + 1), s));
     h->prof_end(KID_ASM, ev, 0.0, s);
-    for (const auto &st : pl.s1_steps)
-        if ((rc = run_factor_step<T>(h, st, b, s)) != D3M_OK) return rc;
+    if ((rc = run_factor_sweep<T>(h, pl.s1_steps, b, s)) != D3M_OK) return rc;
     h->prof_begin(ev, s);
     HIPCHK(launch_asm<T>(h->d_asm, (int64_t)pl.asmb.size(), b, s));
     h->prof_end(KID_ASM, ev, 0.0, s);
-    for (const auto &st : pl.k_steps)
-        if ((rc = run_factor_step<T>(h, st, b, s)) != D3M_OK) return rc;
+    if ((rc = run_factor_sweep<T>(h, pl.k_steps, b, s)) != D3M_OK) return rc;
     std::vector<int> status(pl.n_status + 1, 0);
     HIPCHK(hipMemcpyAsync(status.data(), h->d_status, sizeof(int) * status.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -130,6 +130,40 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
     };
     auto E = [](int arr, i64 slot_) { return enc(arr, slot_ * TILE_ELEMS); };
 
+    // ----------------------------- tile pattern of M_d after elimination --
+    // nz[d][a][b] (b <= a): tile (a, b) of M_d is structurally nonzero after
+    // the first TE[d] tile columns are eliminated.  Interchanges stay inside
+    // a diagonal tile, so the tile pattern does not depend on the pivots.
+    // Edges are numbered lexicographically from the mesh, so A_d is banded and
+    // the multiplier rows meet only interface edges: most tiles stay zero and
+    // are never touched (no panel, update or solve work on them).
+    std::vector<std::vector<std::vector<char>>> nz(N);
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        const int T = pl.T[d];
+        auto &P = nz[d];
+        P.assign(T, std::vector<char>(T, 0));
+        for (int a = 0; a < T; ++a) P[a][a] = 1;
+        for (size_t x = 0; x < S.a_row.size(); ++x) P[S.a_row[x] / TILE][S.a_col[x] / TILE] = 1;
+        for (size_t ob = 0; ob < S.blocks.size(); ++ob) {
+            const int Pb = S.blocks[ob];
+            for (i64 l = dc.blk_start[Pb]; l < dc.blk_start[Pb + 1]; ++l) {
+                const i64 r = (i64)pl.TE[d] * TILE + S.block_off[ob] + (l - dc.blk_start[Pb]);
+                P[r / TILE][S.row_of(dc.lm_e[l]) / TILE] = 1;
+            }
+        }
+        for (int j = 0; j < pl.TE[d]; ++j)
+            for (int x = j + 1; x < T; ++x) {
+                if (!P[x][j]) continue;
+                for (int y = j + 1; y <= x; ++y)
+                    if (P[y][j]) P[x][y] = 1;
+            }
+    }
+    pl.s1_tiles = 0;
+    for (int d = 0; d < N; ++d)
+        for (int a = 0; a < pl.T[d]; ++a)
+            for (int b = 0; b <= a && b < pl.TE[d]; ++b) pl.s1_tiles += nz[d][a][b];
+
     // --------------------------------------------- step 1 (subdomain) plan --
     for (int j = 0; j < maxTE; ++j) {
         FactorStep st;
@@ -155,7 +189,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
             if (j >= pl.TE[d]) continue;
             int w = mrows(d, j);
             for (int a = j + 1; a < pl.T[d]; ++a) {
-                if (a >= pl.TE[d] && j < pl.fb[d]) continue;
+                if (!nz[d][a][j]) continue;
                 pl.gemm.push_back({E(ARR_MX, mslot(d, a, j)), (int32_t)pl.pairs.size(), 1});
                 pl.pairs.push_back({E(ARR_M, mslot(d, a, j)), E(ARR_TT, pl.tt_s1[d] + j)});
                 ScaleTask s{};
@@ -172,20 +206,27 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         }
         st.npan = (i64)pl.gemm.size() - st.pan0;
         st.nsc = (i64)pl.scale.size() - st.sc0;
-        // trailing updates M(a, b) -= X(a, j) L-hat(b, j)^T
+        // trailing updates M(a, b) -= X(a, j) L-hat(b, j)^T; the tiles of
+        // column j + 1 (next step's diagonal and panel) come first
         st.up0 = (i64)pl.gemm.size();
-        for (int d = 0; d < N; ++d) {
-            if (j >= pl.TE[d]) continue;
-            int w = mrows(d, j);
-            for (int b = j + 1; b < pl.T[d]; ++b)
-                for (int a = b; a < pl.T[d]; ++a) {
-                    if (a >= pl.TE[d] && j < pl.fb[d]) continue;
-                    pl.gemm.push_back({E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 1});
-                    pl.pairs.push_back({E(ARR_MX, mslot(d, a, j)), E(ARR_M, mslot(d, b, j))});
-                    int ra = mrows(d, a), rb = mrows(d, b);
-                    double f = 8.0 * w * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
-                    st.up_flops += f;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int d = 0; d < N; ++d) {
+                if (j >= pl.TE[d]) continue;
+                int w = mrows(d, j);
+                for (int b = j + 1; b < pl.T[d]; ++b) {
+                    if ((b == j + 1) != (pass == 0) || !nz[d][b][j]) continue;
+                    for (int a = b; a < pl.T[d]; ++a) {
+                        if (!nz[d][a][j]) continue;
+                        pl.gemm.push_back({E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 1});
+                        pl.pairs.push_back({E(ARR_MX, mslot(d, a, j)), E(ARR_M, mslot(d, b, j))});
+                        int ra = mrows(d, a), rb = mrows(d, b);
+                        double f = 8.0 * w * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                        st.up_flops += f;
+                        if (pass == 0) st.crit_flops += f;
+                    }
                 }
+            }
+            if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
         }
         st.nup = (i64)pl.gemm.size() - st.up0;
         pl.flops_s1 += st.up_flops;
@@ -287,22 +328,29 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
             for (size_t x = 0; x < ustruct[j].size(); ++x)
                 for (size_t y = 0; y <= x; ++y)
                     targets[{ustruct[j][x], ustruct[j][y]}].push_back(j);
+        // targets in block columns of the next level first
         st.up0 = (i64)pl.gemm.size();
-        for (auto &kv : targets) {
-            int i = kv.first.first, k = kv.first.second;
-            for (int b = 0; b < pl.kt[k]; ++b)
-                for (int a = (i == k ? b : 0); a < pl.kt[i]; ++a) {
-                    GemmTask g{E(ARR_K, kslot(k, i, a, b)), (int32_t)pl.pairs.size(), 0};
-                    int ra = tile_rows(nsz[i], a), rb = tile_rows(nsz[k], b);
-                    for (int j : kv.second)
-                        for (int c = 0; c < pl.kt[j]; ++c) {
-                            pl.pairs.push_back({E(ARR_KX, kslot(j, i, a, c)), E(ARR_KL, kslot(j, k, b, c))});
-                            ++g.np;
-                            int w = tile_rows(nsz[j], c);
-                            st.up_flops += 8.0 * w * ((i == k && a == b) ? ra * (ra + 1) / 2.0 : (double)ra * rb);
-                        }
-                    pl.gemm.push_back(g);
-                }
+        for (int pass = 0; pass < 2; ++pass) {
+            for (auto &kv : targets) {
+                int i = kv.first.first, k = kv.first.second;
+                if ((ulevel[k] == L + 1) != (pass == 0)) continue;
+                for (int b = 0; b < pl.kt[k]; ++b)
+                    for (int a = (i == k ? b : 0); a < pl.kt[i]; ++a) {
+                        GemmTask g{E(ARR_K, kslot(k, i, a, b)), (int32_t)pl.pairs.size(), 0};
+                        int ra = tile_rows(nsz[i], a), rb = tile_rows(nsz[k], b);
+                        for (int j : kv.second)
+                            for (int c = 0; c < pl.kt[j]; ++c) {
+                                pl.pairs.push_back({E(ARR_KX, kslot(j, i, a, c)), E(ARR_KL, kslot(j, k, b, c))});
+                                ++g.np;
+                                int w = tile_rows(nsz[j], c);
+                                double f = 8.0 * w * ((i == k && a == b) ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                                st.up_flops += f;
+                                if (pass == 0) st.crit_flops += f;
+                            }
+                        pl.gemm.push_back(g);
+                    }
+            }
+            if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
         }
         st.nup = (i64)pl.gemm.size() - st.up0;
         pl.flops_s3 += st.up_flops;
@@ -403,7 +451,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         for (int d = 0; d < N; ++d) {
             if (j >= pl.TE[d]) continue;
             for (int a = j + 1; a < pl.T[d]; ++a) {
-                if (a >= pl.TE[d] && j < pl.fb[d]) continue;
+                if (!nz[d][a][j]) continue;
                 pl.vupd.push_back({V(V_X, pl.vs1[d] + a), (int32_t)pl.vpairs.size(), 1});
                 pl.vpairs.push_back({E(ARR_M, mslot(d, a, j)), V(V_Y, pl.vs1[d] + j)});
             }
@@ -493,11 +541,11 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         for (int d = 0; d < N; ++d)
             for (int c = 0; c < pl.TE[d]; ++c) {
                 VUpdTask u{V(V_ACC, pl.vs1[d] + c), (int32_t)pl.vpairs.size(), 0};
-                if (c >= pl.fb[d])
-                    for (int a = pl.TE[d]; a < pl.T[d]; ++a) {
-                        pl.vpairs.push_back({E(ARR_M, mslot(d, a, c)), V(V_X, pl.vs1[d] + a)});
-                        ++u.np;
-                    }
+                for (int a = pl.TE[d]; a < pl.T[d]; ++a) {
+                    if (!nz[d][a][c]) continue;
+                    pl.vpairs.push_back({E(ARR_M, mslot(d, a, c)), V(V_X, pl.vs1[d] + a)});
+                    ++u.np;
+                }
                 pl.vupd.push_back(u);
             }
         st.nup = (i64)pl.vupd.size() - st.up0;
@@ -522,6 +570,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         for (int d = 0; d < N; ++d) {
             if (j >= pl.TE[d]) continue;
             for (int c = 0; c < j; ++c) {
+                if (!nz[d][j][c]) continue;
                 pl.vupd.push_back({V(V_ACC, pl.vs1[d] + c), (int32_t)pl.vpairs.size(), 1});
                 pl.vpairs.push_back({E(ARR_M, mslot(d, j, c)), V(V_X, pl.vs1[d] + j)});
             }
@@ -532,10 +581,10 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
 
     // ------------------------------------------------ algorithmic counts --
     i64 ent = 0;
-    for (int d = 0; d < N; ++d) {
-        const Subdomain &S = dc.sub[d];
-        for (i64 c = 0; c < S.n; ++c) ent += (S.n - c - 1) + (c >= S.nI ? S.m : 0);
-    }
+    for (int d = 0; d < N; ++d)  // stored factor tiles of step 1 (diagonal ones are half)
+        for (int a = 0; a < pl.T[d]; ++a)
+            for (int b = 0; b <= a && b < pl.TE[d]; ++b)
+                if (nz[d][a][b]) ent += (a == b) ? (i64)mrows(d, a) * (mrows(d, a) - 1) / 2 : (i64)mrows(d, a) * mrows(d, b);
     for (int j = 0; j < nb; ++j) {
         ent += (i64)nsz[j] * (nsz[j] - 1) / 2;
         for (int i : ustruct[j]) ent += (i64)nsz[i] * nsz[j];

@@ -17,7 +17,9 @@ struct FactorStep {
     i64 pan0 = 0, npan = 0;
     i64 sc0 = 0, nsc = 0;
     i64 up0 = 0, nup = 0;
+    i64 ncrit = 0;           // the first ncrit update tasks target the next step's block columns
     double up_flops = 0.0;   // algorithmic flops of the update GEMMs
+    double crit_flops = 0.0; // ... of which in the first ncrit tasks
     double pan_flops = 0.0;  // algorithmic flops of the panels (triangular solves)
 };
 
@@ -35,6 +37,7 @@ struct Plan {
     std::vector<int> TE, TL, T, fb;    // E tiles, LM tiles, total, first tile column holding interface rows
     std::vector<i64> m_base;           // tile slot of tile (0,0) of each subdomain in ARR_M
     i64 m_tiles = 0;
+    i64 s1_tiles = 0;                  // structurally nonzero tiles in the eliminated columns
     // ---- LM Schur complement (-K), elimination-position order -----------
     // Units are the blocks of K in elimination order, or pieces of them
     // (consecutive rows of one block) when the pivot scope is restricted.

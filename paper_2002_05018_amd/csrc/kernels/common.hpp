@@ -30,13 +30,21 @@ __device__ __forceinline__ double2 cfms(double2 a, double2 b, double2 c) {
 __device__ __forceinline__ double2 cfma_neg(double2 a, double2 b, double2 c) {
     return make_double2(fma(-b.x, c.x, fma(b.y, c.y, a.x)), fma(-b.x, c.y, fma(-b.y, c.x, a.y)));
 }
-// 1/z from the definition conj(z)/|z|^2 (scaled to avoid overflow)
+// 1/z from the definition conj(z)/|z|^2.  z is first scaled by a power of
+// two that brings its larger component near 1 (exact, no overflow in |z|^2);
+// 1/|z|^2 is the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - d r) (each roughly doubles the correct bits).  A zero
+// or non-finite z gives a non-finite result, as the division would.
 __device__ __forceinline__ double2 crecip(double2 z) {
-    const double s = fmax(fabs(z.x), fabs(z.y));
-    const double is = 1.0 / s;
-    const double xr = z.x * is, xi = z.y * is;
-    const double id = 1.0 / ((xr * xr + xi * xi) * s);
-    return make_double2(xr * id, -xi * id);
+    const double m = fmax(fabs(z.x), fabs(z.y));
+    const int e = m > 0.0 && m <= 1.7e308 ? __builtin_amdgcn_frexp_exp(m) : 0;
+    const double xr = ldexp(z.x, -e), xi = ldexp(z.y, -e);
+    const double d = fma(xr, xr, xi * xi);
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    if (!(m > 0.0)) r = 1.0 / d;  // keeps the non-finite result of a zero pivot
+    return make_double2(ldexp(xr * r, -e), -ldexp(xi * r, -e));
 }
 __device__ __forceinline__ double cabs1(double2 z) { return fabs(z.x) + fabs(z.y); }
 

@@ -573,12 +573,26 @@ template <> struct Mfma<float> {
     }
 };
 
+// Work-groups are dealt to the 8 XCDs round-robin (group g runs on XCD g % 8),
+// each with its own L2.  Task lists are ordered so that neighbouring tasks
+// share operand tiles (same subdomain and block column), so XCD x is given
+// the contiguous range of tasks [x * per, (x + 1) * per): g -> (g % 8) * per
+// + g / 8.  The grid is 8 * per groups; the few beyond ntask exit at once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_task(int64_t ntask) {
+    const int64_t per = (ntask + kXcds - 1) / kXcds;
+    return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, const GemmPair *pairs, Bases bases) {
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
+                                                      Bases bases) {
     using T2 = typename C2T<T>::type;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
-    const GemmTask tk = tasks[blockIdx.x];
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const GemmTask tk = tasks[task];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
@@ -738,10 +752,11 @@ template <typename T>
 hipError_t launch_gemm(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs, const Bases &b, int mode,
                        hipStream_t s) {
     if (ntask <= 0) return hipSuccess;
+    const unsigned groups = (unsigned)(((ntask + kXcds - 1) / kXcds) * kXcds);
     if (mode == 0)
-        hipLaunchKernelGGL((gemm_nt_kernel<T, 0>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, pairs, b);
+        hipLaunchKernelGGL((gemm_nt_kernel<T, 0>), dim3(groups), dim3(256), 0, s, tasks, ntask, pairs, b);
     else
-        hipLaunchKernelGGL((gemm_nt_kernel<T, 1>), dim3((unsigned)ntask), dim3(256), 0, s, tasks, pairs, b);
+        hipLaunchKernelGGL((gemm_nt_kernel<T, 1>), dim3(groups), dim3(256), 0, s, tasks, ntask, pairs, b);
     return hipGetLastError();
 }
 
