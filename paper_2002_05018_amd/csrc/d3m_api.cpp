@@ -336,6 +336,8 @@ VBases vbases_of(d3m_problem *h) {
 // next-column updates of step j wait for the side-stream updates of step
 // j - 1 (which also reach those columns), and a side-stream launch starts
 // only after the panels it reads are scaled.
+constexpr i64 kLookaheadMinTasks = 512;
+
 template <typename T>
 int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
     hipStream_t s2 = h->side;
@@ -353,20 +355,26 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
             HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
             h->prof_end(KID_PANEL, ev, st.pan_flops, s);
         }
-        const i64 nrest = st.nup - st.ncrit;
+        // small updates stay on one stream: a cross-stream hand-off costs
+        // more than the overlap gains when the side launch is short
+        const bool split = st.nup - st.ncrit >= kLookaheadMinTasks;
+        const i64 ncrit = split ? st.ncrit : st.nup;
+        const double crit_flops = split ? st.crit_flops : st.up_flops;
+        const i64 nrest = st.nup - ncrit;
         if (nrest > 0) {
             hipEvent_t scaled = h->sync_event();
             HIPCHK(hipEventRecord(scaled, s));
             HIPCHK(hipStreamWaitEvent(s2, scaled, 0));
             h->prof_begin(ev, s2);
-            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + st.ncrit, nrest, h->d_pairs, b, 1, s2));
-            h->prof_end(KID_UPDATE, ev, st.up_flops - st.crit_flops, s2);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + ncrit, nrest, h->d_pairs, b, 1, s2));
+            h->prof_end(KID_UPDATE, ev, st.up_flops - crit_flops, s2);
         }
         if (rest_done) HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
-        if (st.ncrit > 0) {  // timed only when launched, so averages are per launch
+        rest_done = nullptr;
+        if (ncrit > 0) {  // timed only when launched, so averages are per launch
             h->prof_begin(ev, s);
-            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.ncrit, h->d_pairs, b, 1, s));
-            h->prof_end(KID_UPDATE, ev, st.crit_flops, s);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, ncrit, h->d_pairs, b, 1, s));
+            h->prof_end(KID_UPDATE, ev, crit_flops, s);
         }
         if (nrest > 0) {
             rest_done = h->sync_event();
