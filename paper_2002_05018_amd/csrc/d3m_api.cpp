@@ -351,8 +351,13 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
         }
         if (st.npan > 0 || st.nsc > 0) {
             h->prof_begin(ev, s);
-            HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
-            HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+            if (st.fused_scale) {
+                HIPCHK(launch_panel_scale<T>(h->d_gemm + st.pan0, h->d_scale + st.sc0, st.npan, h->d_pairs, b, h->D,
+                                             s));
+            } else {
+                HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+                HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+            }
             h->prof_end(KID_PANEL, ev, st.pan_flops, s);
         }
         // small updates stay on one stream: a cross-stream hand-off costs

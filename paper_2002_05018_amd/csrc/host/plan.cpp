@@ -206,6 +206,10 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         }
         st.npan = (i64)pl.gemm.size() - st.pan0;
         st.nsc = (i64)pl.scale.size() - st.sc0;
+        st.fused_scale = st.npan == st.nsc;
+        for (i64 x = st.sc0; x < st.sc0 + st.nsc && st.fused_scale; ++x)
+            st.fused_scale = pl.scale[x].xprev < 0 && pl.scale[x].xnext < 0 &&
+                             pl.scale[x].x == pl.gemm[st.pan0 + (x - st.sc0)].c;
         // trailing updates M(a, b) -= X(a, j) L-hat(b, j)^T; the tiles of
         // column j + 1 (next step's diagonal and panel) come first
         st.up0 = (i64)pl.gemm.size();
@@ -321,6 +325,10 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         }
         st.npan = (i64)pl.gemm.size() - st.pan0;
         st.nsc = (i64)pl.scale.size() - st.sc0;
+        st.fused_scale = st.npan == st.nsc;
+        for (i64 x = st.sc0; x < st.sc0 + st.nsc && st.fused_scale; ++x)
+            st.fused_scale = pl.scale[x].xprev < 0 && pl.scale[x].xnext < 0 &&
+                             pl.scale[x].x == pl.gemm[st.pan0 + (x - st.sc0)].c;
         // updates grouped by target block so that every target tile is
         // written by exactly one work-group (deterministic, atomic-free)
         std::map<std::pair<int, int>, std::vector<int>> targets;

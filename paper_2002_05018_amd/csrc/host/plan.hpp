@@ -16,6 +16,7 @@ struct FactorStep {
     int bk_maxn = 0;
     i64 pan0 = 0, npan = 0;
     i64 sc0 = 0, nsc = 0;
+    bool fused_scale = false;  // panel task i and scale task i are the same single-tile block
     i64 up0 = 0, nup = 0;
     i64 ncrit = 0;           // the first ncrit update tasks target the next step's block columns
     double up_flops = 0.0;   // algorithmic flops of the update GEMMs

@@ -584,19 +584,17 @@ __device__ __forceinline__ int64_t xcd_task(int64_t ntask) {
     return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
-                                                      Bases bases) {
+// Accumulates sum_p A_p B_p^T of one task into the per-wave quadrant
+// accumulators (C^T layout, see above).
+template <typename T>
+__device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases,
+                                              typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]) {
     using T2 = typename C2T<T>::type;
     using M = Mfma<T>;
     using acc_t = typename M::acc;
-    const int64_t task = xcd_task(ntask);
-    if (task >= ntask) return;
-    const GemmTask tk = tasks[task];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    acc_t re[2][2], im[2][2];
     for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 2; ++q) { re[m][q] = acc_t{0, 0, 0, 0}; im[m][q] = acc_t{0, 0, 0, 0}; }
     for (int p = 0; p < tk.np; ++p) {
@@ -622,6 +620,22 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
                 }
         }
     }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
+                                                      Bases bases) {
+    using T2 = typename C2T<T>::type;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const GemmTask tk = tasks[task];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    acc_t re[2][2], im[2][2];
+    gemm_task_acc<T>(tk, pairs, bases, re, im);
     T2 *C = enc_ptr<T2>(bases, tk.c);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -639,6 +653,55 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
                     *c = T2{o.x - re[m][q][r], o.y - im[m][q][r]};
                 }
             }
+}
+
+// Panel of one tile with its scaling fused: X = sum_p A_p B_p^T (stored) and
+// L-hat = X D^{-1} over the tile's own columns (1x1 and 2x2 pivots of a
+// block of one tile never reach a neighbouring tile).  Task i of the panel
+// list and task i of the scale list describe the same tile.
+template <typename T>
+__global__ __launch_bounds__(256) void panel_scale_kernel(const GemmTask *tasks, const ScaleTask *stasks,
+                                                          int64_t ntask, const GemmPair *pairs, Bases bases,
+                                                          DArrays D) {
+    using T2 = typename C2T<T>::type;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    __shared__ T2 xs[64 * 65];
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const GemmTask tk = tasks[task];
+    const ScaleTask sk = stasks[task];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    acc_t re[2][2], im[2][2];
+    gemm_task_acc<T>(tk, pairs, bases, re, im);
+    T2 *C = enc_ptr<T2>(bases, tk.c);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wr + 16 * m + li;
+                const int col = wc + 16 * q + M::out_row(lk, r);
+                const T2 v = T2{re[m][q][r], im[m][q][r]};
+                C[col * 64 + row] = v;
+                xs[col * 65 + row] = v;
+            }
+    __syncthreads();
+    T2 *W = enc_ptr<T2>(bases, sk.w);
+    for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+        const int r = e & 63, c = e >> 6;
+        double2 out = make_double2(0, 0);
+        if (c < sk.ncols) {
+            const int64_t row = sk.drow + c;
+            const int pv = D.piv[row];
+            out = cmul(to_d2(xs[c * 65 + r]), D.dinv[row]);
+            if (pv != 0) out = cadd(out, cmul(to_d2(xs[(c + pv) * 65 + r]), D.dinvoff[row]));
+        }
+        W[e] = from_d2<T2>(out);
+    }
 }
 
 // ------------------------------------------------- L-hat = X D^{-1} -----
@@ -761,6 +824,15 @@ hipError_t launch_gemm(const GemmTask *tasks, int64_t ntask, const GemmPair *pai
 }
 
 template <typename T>
+hipError_t launch_panel_scale(const GemmTask *tasks, const ScaleTask *stasks, int64_t ntask, const GemmPair *pairs,
+                              const Bases &b, const DArrays &D, hipStream_t s) {
+    if (ntask <= 0) return hipSuccess;
+    const unsigned groups = (unsigned)(((ntask + kXcds - 1) / kXcds) * kXcds);
+    hipLaunchKernelGGL((panel_scale_kernel<T>), dim3(groups), dim3(256), 0, s, tasks, stasks, ntask, pairs, b, D);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_scale(const ScaleTask *tasks, int64_t ntask, const Bases &b, const DArrays &D, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
@@ -783,6 +855,8 @@ hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipSt
                                      double2 *, hipStream_t);                                                 \
     template hipError_t launch_gemm<T>(const GemmTask *, int64_t, const GemmPair *, const Bases &, int,        \
                                        hipStream_t);                                                          \
+    template hipError_t launch_panel_scale<T>(const GemmTask *, const ScaleTask *, int64_t, const GemmPair *,   \
+                                              const Bases &, const DArrays &, hipStream_t);                   \
     template hipError_t launch_scale<T>(const ScaleTask *, int64_t, const Bases &, const DArrays &,            \
                                         hipStream_t);                                                         \
     template hipError_t launch_asm<T>(const AsmTask *, int64_t, const Bases &, hipStream_t);
