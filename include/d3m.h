@@ -75,8 +75,10 @@ typedef struct {
     int32_t quad_points;  /* Gauss points per direction of the collapsed
                              triangle rule for the plane-wave load (default 12) */
     int32_t ir_max_iter;  /* FP32_IR: maximum refinement steps (default 10)  */
-    int32_t profile;      /* 1: time every kernel launch with HIP events (for
-                             d3m_kernel_stats); adds a little launch overhead */
+    int32_t profile;      /* timing with HIP events for d3m_kernel_stats:
+                             0 off, 1 the update GEMM launches only, 2 every
+                             kernel group (each timed launch adds a little
+                             overhead; 2 adds about a tenth at config 2)      */
     double ir_tol;        /* FP32_IR: stop when max over right-hand sides of
                              ||f - S E||_inf / ||f||_inf <= ir_tol (1e-10)   */
     int32_t use_graph;    /* reserved (0)                                     */
@@ -187,7 +189,11 @@ int d3m_query(d3m_handle h, d3m_info *info);
 void d3m_destroy(d3m_handle h);
 const char *d3m_last_error(void);
 
-/* Per-kernel timings recorded while opt.profile = 1 (reset by this call when
+/* Change the profiling level of opt.profile (0, 1 or 2) for later calls.
+ * Returns D3M_EINVAL for another level or a null handle. */
+int d3m_set_profile(d3m_handle h, int level);
+
+/* Per-kernel timings recorded while opt.profile > 0 (reset by this call when
  * reset != 0).  kernel: 0 update GEMM, 1 panel GEMM, 2 Bunch-Kaufman block,
  * 3 scatter/assembly, 4 solve sweeps, 5 refinement residual.  Outputs: number
  * of launches, summed launch milliseconds and algorithmic flops. */

@@ -29,7 +29,8 @@ EXPORT = {"edges": 1, "sub_edges": 2, "sub_ni": 3, "a_coo": 4, "lms": 5, "order"
 # symbols declared in include/d3m.h
 exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_factor",
                     "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
-                    "d3m_destroy", "d3m_last_error", "d3m_kernel_stats", "d3m_debug_export"]
+                    "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
+                    "d3m_debug_export"]
 
 
 class d3m_c128(C.Structure):
@@ -82,8 +83,9 @@ _lib.d3m_kernel_stats.argtypes = [_h, C.c_int, C.c_int, C.POINTER(C.c_int64), C.
                                   C.POINTER(C.c_double)]
 _lib.d3m_debug_export.argtypes = [_h, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
 _lib.d3m_debug_export.restype = C.c_int64
+_lib.d3m_set_profile.argtypes = [_h, C.c_int]
 for _f in ("d3m_setup", "d3m_update_eps", "d3m_factor", "d3m_solve", "d3m_adjoint",
-           "d3m_rhs_planewave", "d3m_probe", "d3m_query", "d3m_kernel_stats"):
+           "d3m_rhs_planewave", "d3m_probe", "d3m_query", "d3m_set_profile", "d3m_kernel_stats"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -127,7 +129,8 @@ class Solver:
         opt = d3m_options()
         _lib.d3m_default_options(C.byref(opt))
         opt.host_only = int(host_only)
-        opt.profile = int(profile)
+        # True: every kernel group; an int: that level (0 off, 1 update GEMMs, 2 all)
+        opt.profile = 2 if profile is True else int(profile)
         opt.device = int(device)
         opt.quad_points = int(quad_points)
         opt.ir_tol = float(ir_tol)
@@ -225,6 +228,10 @@ class Solver:
         inf = d3m_info()
         _check(_lib.d3m_query(self._handle, C.byref(inf)))
         return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name != "reserved"}
+
+    def set_profile(self, level):
+        """Profiling level for later calls: 0 off, 1 update GEMMs only, 2 all."""
+        _check(_lib.d3m_set_profile(self._handle, int(level)))
 
     def kernel_stats(self, kernel, reset=False):
         kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel)

@@ -146,8 +146,11 @@ struct d3m_problem {
     }
 
     // ---- profiling helpers
-    void prof_begin(hipEvent_t &a, hipStream_t s) {
-        if (!opt.profile) return;
+    // opt.profile: 0 off, 1 the update GEMMs only, 2 every kernel group
+    bool prof_wanted(int kid) const { return opt.profile >= 2 || (opt.profile == 1 && kid == KID_UPDATE); }
+    void prof_begin(int kid, hipEvent_t &a, hipStream_t s) {
+        a = nullptr;
+        if (!prof_wanted(kid)) return;
         if (ev_next + 2 > ev_pool.size()) {
             for (int i = 0; i < 256; ++i) { hipEvent_t e; if (hipEventCreate(&e) == hipSuccess) ev_pool.push_back(e); }
         }
@@ -155,13 +158,12 @@ struct d3m_problem {
         (void)hipEventRecord(a, s);
     }
     void prof_end(int kid, hipEvent_t a, double flops, hipStream_t s) {
-        if (!opt.profile) return;
+        if (!a) return;
         hipEvent_t b = ev_pool[ev_next++];
         (void)hipEventRecord(b, s);
         recs.push_back({kid, a, b, flops});
     }
     void prof_collect() {
-        if (!opt.profile) return;
         for (auto &r : recs) {
             float ms = 0.f;
             (void)hipEventSynchronize(r.b);
@@ -345,12 +347,12 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
     for (const auto &st : steps) {
         hipEvent_t ev{};
         if (st.nbk > 0) {
-            h->prof_begin(ev, s);
+            h->prof_begin(KID_BK, ev, s);
             HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
             h->prof_end(KID_BK, ev, 0.0, s);
         }
         if (st.npan > 0 || st.nsc > 0) {
-            h->prof_begin(ev, s);
+            h->prof_begin(KID_PANEL, ev, s);
             if (st.fused_scale) {
                 HIPCHK(launch_panel_scale<T>(h->d_gemm + st.pan0, h->d_scale + st.sc0, st.npan, h->d_pairs, b, h->D,
                                              s));
@@ -370,14 +372,14 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
             hipEvent_t scaled = h->sync_event();
             HIPCHK(hipEventRecord(scaled, s));
             HIPCHK(hipStreamWaitEvent(s2, scaled, 0));
-            h->prof_begin(ev, s2);
+            h->prof_begin(KID_UPDATE, ev, s2);
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + ncrit, nrest, h->d_pairs, b, 1, s2));
             h->prof_end(KID_UPDATE, ev, st.up_flops - crit_flops, s2);
         }
         if (rest_done) HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
         rest_done = nullptr;
         if (ncrit > 0) {  // timed only when launched, so averages are per launch
-            h->prof_begin(ev, s);
+            h->prof_begin(KID_UPDATE, ev, s);
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, ncrit, h->d_pairs, b, 1, s));
             h->prof_end(KID_UPDATE, ev, crit_flops, s);
         }
@@ -397,13 +399,13 @@ int factor_impl(d3m_problem *h, hipStream_t s) {
     const Plan &pl = h->pl;
     Bases b = bases_of<T>(h);
     hipEvent_t ev{};
-    h->prof_begin(ev, s);
+    h->prof_begin(KID_ASM, ev, s);
     HIPCHK(launch_fill_zero<T>(b.p[ARR_M], pl.m_tiles * TILE_ELEMS, s));
     HIPCHK(launch_coo_scatter<T>(b.p[ARR_M], h->d_coo_off, h->d_coo_val, (int64_t)pl.coo_off.size(), s));
     HIPCHK(hipMemsetAsync(h->d_status, 0, sizeof(int) * (pl.n_status + 1), s));
     h->prof_end(KID_ASM, ev, 0.0, s);
     if ((rc = run_factor_sweep<T>(h, pl.s1_steps, b, s)) != D3M_OK) return rc;
-    h->prof_begin(ev, s);
+    h->prof_begin(KID_ASM, ev, s);
     HIPCHK(launch_asm<T>(h->d_asm, (int64_t)pl.asmb.size(), b, s));
     h->prof_end(KID_ASM, ev, 0.0, s);
     if ((rc = run_factor_sweep<T>(h, pl.k_steps, b, s)) != D3M_OK) return rc;
@@ -448,7 +450,7 @@ int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accu
     Bases b = bases_of<T>(h);
     VBases vb = vbases_of<T>(h);
     hipEvent_t ev{};
-    h->prof_begin(ev, s);
+    h->prof_begin(KID_SOLVE, ev, s);
     HIPCHK(launch_vsplit<T>(vb.p[V_X], f, h->d_split, pl.v_tiles_s1 * 64, nrhs, h->mesh.ne, s));
     for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
     HIPCHK(launch_vgather_h<T>(vb.p[V_KX], vb.p[V_X], h->d_hmap, pl.v_tiles_k * 64, nrhs, s));
@@ -490,7 +492,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         if (info) {
             if ((rc = h->ensure(h->stage_r, vbytes))) return rc;
             hipEvent_t ev{};
-            h->prof_begin(ev, s);
+            h->prof_begin(KID_RESID, ev, s);
             HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
             h->prof_end(KID_RESID, ev, 0.0, s);
             std::vector<double> rn, fn;
@@ -517,7 +519,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     bool ok = false;
     for (;;) {
         hipEvent_t ev{};
-        h->prof_begin(ev, s);
+        h->prof_begin(KID_RESID, ev, s);
         HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
         h->prof_end(KID_RESID, ev, 0.0, s);
         if ((rc = norms_inf(h, (double2 *)h->stage_r.p, nrhs, rn, s))) return rc;
@@ -546,6 +548,13 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
 extern "C" {
 
 const char *d3m_last_error(void) { return g_err.c_str(); }
+
+int d3m_set_profile(d3m_handle h, int level) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (level < 0 || level > 2) return fail(D3M_EINVAL, "profile level must be 0, 1 or 2");
+    h->opt.profile = level;
+    return D3M_OK;
+}
 
 void d3m_default_options(d3m_options *o) {
     if (!o) return;
