@@ -376,14 +376,16 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + ncrit, nrest, h->d_pairs, b, 1, s2));
             h->prof_end(KID_UPDATE, ev, st.up_flops - crit_flops, s2);
         }
-        if (rest_done) HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
-        rest_done = nullptr;
+        if (rest_done && st.wait_rest) {
+            HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
+            rest_done = nullptr;
+        }
         if (ncrit > 0) {  // timed only when launched, so averages are per launch
             h->prof_begin(KID_UPDATE, ev, s);
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, ncrit, h->d_pairs, b, 1, s));
             h->prof_end(KID_UPDATE, ev, crit_flops, s);
         }
-        if (nrest > 0) {
+        if (nrest > 0) {  // (a step with side updates always waited above, so nothing is lost)
             rest_done = h->sync_event();
             HIPCHK(hipEventRecord(rest_done, s2));
         }

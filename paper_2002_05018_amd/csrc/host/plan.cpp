@@ -19,6 +19,8 @@ namespace d3m {
 namespace {
 inline int ceil_div(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total - (i64)t * TILE); }
+// tile columns of M_d whose Schur updates beyond the block are applied together
+constexpr int S1_BLOCK = 4;
 }  // namespace
 
 void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) {
@@ -210,27 +212,56 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) 
         for (i64 x = st.sc0; x < st.sc0 + st.nsc && st.fused_scale; ++x)
             st.fused_scale = pl.scale[x].xprev < 0 && pl.scale[x].xnext < 0 &&
                              pl.scale[x].x == pl.gemm[st.pan0 + (x - st.sc0)].c;
-        // trailing updates M(a, b) -= X(a, j) L-hat(b, j)^T; the tiles of
-        // column j + 1 (next step's diagonal and panel) come first
+        // Trailing updates M(a, b) -= sum_j' X(a, j') L-hat(b, j')^T, blocked
+        // by S1_BLOCK tile columns [j0, jend): an inner step updates only the
+        // remaining columns of its block (one pair per target), the last step
+        // of a block updates every column beyond it with the pairs of all
+        // the block's columns at once (the target tile is read and written
+        // once per block).  Targets in the next block's columns come first.
+        const int j0 = (j / S1_BLOCK) * S1_BLOCK, jend = std::min(j0 + S1_BLOCK, maxTE);
         st.up0 = (i64)pl.gemm.size();
-        for (int pass = 0; pass < 2; ++pass) {
+        if (j + 1 < jend) {
             for (int d = 0; d < N; ++d) {
                 if (j >= pl.TE[d]) continue;
-                int w = mrows(d, j);
-                for (int b = j + 1; b < pl.T[d]; ++b) {
-                    if ((b == j + 1) != (pass == 0) || !nz[d][b][j]) continue;
+                const int w = mrows(d, j);
+                for (int b = j + 1; b < std::min(jend, pl.T[d]); ++b) {
+                    if (!nz[d][b][j]) continue;
                     for (int a = b; a < pl.T[d]; ++a) {
                         if (!nz[d][a][j]) continue;
                         pl.gemm.push_back({E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 1});
                         pl.pairs.push_back({E(ARR_MX, mslot(d, a, j)), E(ARR_M, mslot(d, b, j))});
                         int ra = mrows(d, a), rb = mrows(d, b);
-                        double f = 8.0 * w * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
-                        st.up_flops += f;
-                        if (pass == 0) st.crit_flops += f;
+                        st.up_flops += 8.0 * w * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
                     }
                 }
             }
-            if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
+            st.ncrit = (i64)pl.gemm.size() - st.up0;
+            st.crit_flops = st.up_flops;
+            st.wait_rest = false;
+        } else {
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int d = 0; d < N; ++d) {
+                    const int jlast = std::min(jend, pl.TE[d]);
+                    if (j0 >= jlast) continue;
+                    for (int b = jend; b < pl.T[d]; ++b) {
+                        if ((b < jend + S1_BLOCK) != (pass == 0)) continue;
+                        for (int a = b; a < pl.T[d]; ++a) {
+                            GemmTask g{E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 0};
+                            const int ra = mrows(d, a), rb = mrows(d, b);
+                            for (int jj = j0; jj < jlast; ++jj) {
+                                if (!nz[d][a][jj] || !nz[d][b][jj]) continue;
+                                pl.pairs.push_back({E(ARR_MX, mslot(d, a, jj)), E(ARR_M, mslot(d, b, jj))});
+                                ++g.np;
+                                const double f = 8.0 * mrows(d, jj) * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                                st.up_flops += f;
+                                if (pass == 0) st.crit_flops += f;
+                            }
+                            if (g.np > 0) pl.gemm.push_back(g);
+                        }
+                    }
+                }
+                if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
+            }
         }
         st.nup = (i64)pl.gemm.size() - st.up0;
         pl.flops_s1 += st.up_flops;

@@ -19,6 +19,7 @@ struct FactorStep {
     bool fused_scale = false;  // panel task i and scale task i are the same single-tile block
     i64 up0 = 0, nup = 0;
     i64 ncrit = 0;           // the first ncrit update tasks target the next step's block columns
+    bool wait_rest = true;   // updates may touch tiles of the previous side-stream updates
     double up_flops = 0.0;   // algorithmic flops of the update GEMMs
     double crit_flops = 0.0; // ... of which in the first ncrit tasks
     double pan_flops = 0.0;  // algorithmic flops of the panels (triangular solves)

@@ -597,26 +597,40 @@ __device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair
     const int li = lane & 15, lk = lane >> 4;
     for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 2; ++q) { re[m][q] = acc_t{0, 0, 0, 0}; im[m][q] = acc_t{0, 0, 0, 0}; }
+    // operands of k-step s + 2 are loaded while k-step s runs
+    constexpr int PF = 2;
     for (int p = 0; p < tk.np; ++p) {
         const GemmPair pr = pairs[tk.p0 + p];
         const T2 *A = enc_ptr<T2>(bases, pr.a);
         const T2 *B = enc_ptr<T2>(bases, pr.b);
-#pragma unroll 4
+        T2 w[PF][2], x[PF][2];
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            const int kcol = (4 * s + lk) * 64;
+            w[s][0] = B[kcol + wc + li];
+            w[s][1] = B[kcol + wc + 16 + li];
+            x[s][0] = A[kcol + wr + li];
+            x[s][1] = A[kcol + wr + 16 + li];
+        }
+#pragma unroll
         for (int k0 = 0; k0 < 64; k0 += 4) {
-            const int kcol = (k0 + lk) * 64;
-            T2 w[2], x[2];
-            w[0] = B[kcol + wc + li];
-            w[1] = B[kcol + wc + 16 + li];
-            x[0] = A[kcol + wr + li];
-            x[1] = A[kcol + wr + 16 + li];
+            const int s = (k0 / 4) % PF;
+            const T2 wq[2] = {w[s][0], w[s][1]}, xm[2] = {x[s][0], x[s][1]};
+            if (k0 + 4 * PF < 64) {
+                const int kcol = (k0 + 4 * PF + lk) * 64;
+                w[s][0] = B[kcol + wc + li];
+                w[s][1] = B[kcol + wc + 16 + li];
+                x[s][0] = A[kcol + wr + li];
+                x[s][1] = A[kcol + wr + 16 + li];
+            }
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    re[m][q] = M::mma(w[q].x, x[m].x, re[m][q]);
-                    re[m][q] = M::mma(-w[q].y, x[m].y, re[m][q]);
-                    im[m][q] = M::mma(w[q].x, x[m].y, im[m][q]);
-                    im[m][q] = M::mma(w[q].y, x[m].x, im[m][q]);
+                    re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
+                    re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
+                    im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
+                    im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
                 }
         }
     }
@@ -634,9 +648,19 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    T2 *C = enc_ptr<T2>(bases, tk.c);
+    // the target tile of an update is loaded first, so its latency overlaps the products
+    T2 cpre[2][2][4];
+    if (MODE == 1) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cpre[m][q][r] = C[(wc + 16 * q + M::out_row(lk, r)) * 64 + wr + 16 * m + li];
+    }
     acc_t re[2][2], im[2][2];
     gemm_task_acc<T>(tk, pairs, bases, re, im);
-    T2 *C = enc_ptr<T2>(bases, tk.c);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -646,12 +670,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
                 const int row = wr + 16 * m + li;
                 const int col = wc + 16 * q + M::out_row(lk, r);
                 T2 *c = C + col * 64 + row;
-                if (MODE == 0) {
-                    *c = T2{re[m][q][r], im[m][q][r]};
-                } else {
-                    T2 o = *c;
-                    *c = T2{o.x - re[m][q][r], o.y - im[m][q][r]};
-                }
+                if (MODE == 0) *c = T2{re[m][q][r], im[m][q][r]};
+                else *c = T2{cpre[m][q][r].x - re[m][q][r], cpre[m][q][r].y - im[m][q][r]};
             }
 }
 
