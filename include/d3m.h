@@ -87,7 +87,11 @@ typedef struct {
                              to: 0 (default) consecutive pieces of at most 64
                              rows of each block of K; 1 whole blocks, as in
                              Algorithm 1 (slower: the search is sequential)  */
-    int32_t reserved[7];
+    int32_t s1_block;     /* tile columns of a subdomain matrix whose Schur
+                             updates beyond them are applied together (one
+                             read-modify-write of each target per block);
+                             0 selects the default 2, at most 16            */
+    int32_t reserved[6];
 } d3m_options;
 
 typedef struct {

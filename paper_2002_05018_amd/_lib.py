@@ -45,8 +45,8 @@ class d3m_mesh(C.Structure):
 class d3m_options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("quad_points", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
-                ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32), ("s1_block", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class d3m_info(C.Structure):
@@ -119,7 +119,7 @@ class Solver:
     """One decomposed problem on the GPU (a d3m_handle)."""
 
     def __init__(self, xyz, tets, part, eps_r, k, alpha, *, host_only=False, profile=False,
-                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10, pivot_scope=0):
+                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10, pivot_scope=0, s1_block=0):
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int64)
         self._part = np.ascontiguousarray(part, dtype=np.int32)
@@ -136,6 +136,7 @@ class Solver:
         opt.ir_tol = float(ir_tol)
         opt.ir_max_iter = int(ir_max_iter)
         opt.pivot_scope = int(pivot_scope)
+        opt.s1_block = int(s1_block)
         a = complex(alpha)
         h = _h()
         _check(_lib.d3m_setup(C.byref(mesh), _ptr(self._part, C.c_int32), _ptr(eps, C.c_double),

@@ -583,7 +583,7 @@ int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r, do
         h->eps.assign(eps_r, eps_r + mesh->n_tets);
         build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
         order_blocks(h->bo, h->dc, h->mesh);
-        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE);
+        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {

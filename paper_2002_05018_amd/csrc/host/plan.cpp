@@ -19,11 +19,11 @@ namespace d3m {
 namespace {
 inline int ceil_div(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total - (i64)t * TILE); }
-// tile columns of M_d whose Schur updates beyond the block are applied together
-constexpr int S1_BLOCK = 4;
+
 }  // namespace
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max) {
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block) {
+    const int S1_BLOCK = std::max(1, std::min(16, s1_block > 0 ? s1_block : 2));
     const int N = dc.N;
     pl = Plan();
 
