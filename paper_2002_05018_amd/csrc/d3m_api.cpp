@@ -65,6 +65,7 @@ struct d3m_problem {
     VDiagTask *d_vdiag = nullptr;
     VUpdTask *d_vupd = nullptr;
     VUpdPair *d_vpairs = nullptr;
+    int64_t *d_vfuse = nullptr;
     int64_t *d_coo_off = nullptr;
     double2 *d_coo_val = nullptr;
     int64_t *d_split = nullptr, *d_collect = nullptr, *d_hmap = nullptr, *d_lmap = nullptr;
@@ -235,6 +236,7 @@ int setup_device(d3m_problem *h) {
     UP(h->d_vdiag, pl.vdiag);
     UP(h->d_vupd, pl.vupd);
     UP(h->d_vpairs, pl.vpairs);
+    UP(h->d_vfuse, pl.vfuse);
     UP(h->d_coo_off, pl.coo_off);
     UP(h->d_split, pl.split_map);
     UP(h->d_collect, pl.collect_map);
@@ -437,9 +439,13 @@ int factor_impl(d3m_problem *h, hipStream_t s) {
 template <typename T>
 int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases &vb, bool bwd, int nrhs,
                hipStream_t s) {
-    if (st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
+    if (st.up_first)
+        HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
+                              vb, h->D, nrhs, s));
     HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, s));
-    if (!st.up_first) HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, st.nup, h->d_vpairs, st.up_mode, b, vb, nrhs, s));
+    if (!st.up_first)
+        HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
+                              vb, h->D, nrhs, s));
     return D3M_OK;
 }
 

@@ -618,6 +618,46 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         pl.s1_bwd.push_back(st);
     }
 
+    // ------------------------------------------- fused update + diagonal --
+    // An update task of step s whose target is the input of a one-tile
+    // diagonal solve of step s + 1 is the last update that input receives
+    // (forward sweeps update blocks of later steps only from earlier ones,
+    // backward sweeps push into blocks of the next step from this one at the
+    // latest), so the task goes on with that solve.  The next step keeps only
+    // the diagonal solves not so fused, moved to the front of its range.
+    pl.vfuse.assign(pl.vupd.size(), -1);
+    auto fuse_sweep = [&](std::vector<SolveStep> &steps, bool bwd) {
+        for (size_t q = 0; q + 1 < steps.size(); ++q) {
+            SolveStep &cur = steps[q], &nxt = steps[q + 1];
+            if (nxt.dg_maxt > 1 || nxt.ndg == 0 || cur.nup == 0) continue;
+            std::map<i64, i64> key2diag;
+            for (i64 i = nxt.dg0; i < nxt.dg0 + nxt.ndg; ++i) key2diag[bwd ? pl.vdiag[i].acc : pl.vdiag[i].x] = i;
+            std::vector<i64> fused_by(nxt.ndg, -1);  // update task fusing diag i
+            for (i64 u = cur.up0; u < cur.up0 + cur.nup; ++u) {
+                auto it = key2diag.find(pl.vupd[u].out);
+                if (it == key2diag.end() || fused_by[it->second - nxt.dg0] >= 0) continue;
+                fused_by[it->second - nxt.dg0] = u;
+            }
+            std::vector<VDiagTask> keep, moved;
+            std::vector<i64> moved_by;
+            for (i64 i = 0; i < nxt.ndg; ++i) {
+                if (fused_by[i] < 0) keep.push_back(pl.vdiag[nxt.dg0 + i]);
+                else { moved.push_back(pl.vdiag[nxt.dg0 + i]); moved_by.push_back(fused_by[i]); }
+            }
+            i64 at = nxt.dg0;
+            for (auto &t : keep) pl.vdiag[at++] = t;
+            for (size_t m = 0; m < moved.size(); ++m) {
+                pl.vfuse[moved_by[m]] = at;
+                pl.vdiag[at++] = moved[m];
+            }
+            nxt.ndg = (i64)keep.size();
+        }
+    };
+    fuse_sweep(pl.s1_fwd, false);
+    fuse_sweep(pl.k_fwd, false);
+    fuse_sweep(pl.k_bwd, true);
+    fuse_sweep(pl.s1_bwd, true);
+
     // ------------------------------------------------ algorithmic counts --
     i64 ent = 0;
     for (int d = 0; d < N; ++d)  // stored factor tiles of step 1 (diagonal ones are half)

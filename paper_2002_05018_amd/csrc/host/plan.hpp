@@ -76,6 +76,7 @@ struct Plan {
     std::vector<VDiagTask> vdiag;
     std::vector<VUpdTask> vupd;
     std::vector<VUpdPair> vpairs;
+    std::vector<int64_t> vfuse;  // per update task: diagonal solve it completes (index into vdiag) or -1
     std::vector<SolveStep> s1_fwd, k_fwd, k_bwd, s1_bwd;
     std::vector<int64_t> h_map;        // per K vector row: the two subdomain vector rows (-1: padding)
     std::vector<int64_t> lam_map;      // per S1 vector row: K vector row of a multiplier row, else -1

@@ -45,8 +45,9 @@ template <typename T>
 hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
                         const DArrays &D, int nrhs, hipStream_t s);
 template <typename T>
-hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pairs, int mode, const Bases &b,
-                       const VBases &vb, int nrhs, hipStream_t s);
+hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
+                       const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
+                       hipStream_t s);
 template <typename T>
 hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s);
 template <typename T>

@@ -140,25 +140,19 @@ __device__ __forceinline__ void reduce_partials(double2 *red, const double (&ax)
 
 // Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y.
 // Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
-// Blocks of one tile (n <= 64); blockIdx.y selects 8 right-hand sides.
-template <typename T2, bool BWD>
-__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
-    __shared__ SolveSmem<T2, BWD> sm;
-    const VDiagTask tk = tasks[blockIdx.x];
-    const int c0 = blockIdx.y * SV_COLS;
+// Blocks of one tile (n <= 64); chunk selects 8 right-hand sides.
+// vdiag_finish applies TT (or TT^T) to the block already staged in sm.xs and
+// writes the outputs.
+template <typename T2, bool BWD, typename Smem>
+__device__ __forceinline__ void vdiag_finish(const VDiagTask &tk, int chunk, const Bases &b, const VBases &vb,
+                                             const DArrays &D, int nrhs, Smem &sm) {
+    const int c0 = chunk * SV_COLS;
     const int ncol = min(SV_COLS, nrhs - c0);
     const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const T2 *TT = enc_ptr<T2>(b, tk.tt);
     double lx[16], ly[16], ax[SV_COLS], ay[SV_COLS];
 #pragma unroll
     for (int c = 0; c < SV_COLS; ++c) ax[c] = ay[c] = 0.0;
-    load_ltile<T2, BWD>(lx, ly, TT, sm.ls);
-    if (BWD) {
-        const T2 *accv = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
-        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.v, nrhs), accv, c0, ncol);
-    } else {
-        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
-    }
+    load_ltile<T2, BWD>(lx, ly, enc_ptr<T2>(b, tk.tt), sm.ls);
     tile_fma(ax, ay, lx, ly, sm.xs, ncol);
     double2 res[2];
     reduce_partials(sm.ls, ax, ay, res);
@@ -198,6 +192,21 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Base
             v[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(live ? val : make_double2(0, 0));
         }
     }
+}
+
+template <typename T2, bool BWD>
+__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
+    __shared__ SolveSmem<T2, BWD> sm;
+    const VDiagTask tk = tasks[blockIdx.x];
+    const int c0 = blockIdx.y * SV_COLS;
+    const int ncol = min(SV_COLS, nrhs - c0);
+    if (BWD) {
+        const T2 *accv = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
+        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.v, nrhs), accv, c0, ncol);
+    } else {
+        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
+    }
+    vdiag_finish<T2, BWD>(tk, blockIdx.y, b, vb, D, nrhs, sm);
 }
 
 // Diagonal blocks of several tiles (blocks larger than 64 factored whole):
@@ -286,13 +295,18 @@ __global__ __launch_bounds__(256) void vdiag_multi_kernel(const VDiagTask *tasks
 }
 
 // out (-=|=|+=) sum_p op(L_p) src_p with op = identity (mode 0) or
-// transpose (modes 1, 2); blockIdx.y selects 8 right-hand sides.
+// transpose (modes 1, 2); blockIdx.y selects 8 right-hand sides.  When
+// fuse[task] >= 0 this update is the last one its target receives before the
+// diagonal solve fuse[task] (forward: the target is that block's x; backward:
+// its accumulator), so the work-group goes on with that solve from the new
+// values kept in LDS, saving a launch per sweep step.
 template <typename T2, int MODE>
-__global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const VUpdPair *pairs, Bases b, VBases vb,
-                                                   int nrhs) {
+__global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const int64_t *fuse, const VUpdPair *pairs,
+                                                   const VDiagTask *vdiag, Bases b, VBases vb, DArrays D, int nrhs) {
     constexpr bool TR = MODE != 0;
     __shared__ SolveSmem<T2, TR> sm;
     const VUpdTask tk = tasks[blockIdx.x];
+    const int64_t fz = fuse[blockIdx.x];
     const int c0 = blockIdx.y * SV_COLS;
     const int ncol = min(SV_COLS, nrhs - c0);
     const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -309,16 +323,29 @@ __global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const 
     double2 res[2];
     reduce_partials(sm.ls, ax, ay, res);
     T2 *out = vptr<T2>(vb, tk.out, nrhs);
+    VDiagTask dg{};
+    const T2 *vin = nullptr;
+    if (fz >= 0) {
+        dg = vdiag[fz];
+        if (TR) vin = vptr<T2>(vb, dg.v, nrhs);
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = w + 4 * h;
         if (c < ncol) {
             T2 *o = out + (int64_t)(c0 + c) * 64 + r;
-            if (MODE == 0) *o = from_d2<T2>(csub(to_d2(*o), res[h]));
-            else if (MODE == 1) *o = from_d2<T2>(res[h]);
-            else *o = from_d2<T2>(cadd(to_d2(*o), res[h]));
+            double2 nw;
+            if (MODE == 0) nw = csub(to_d2(*o), res[h]);
+            else if (MODE == 1) nw = res[h];
+            else nw = cadd(to_d2(*o), res[h]);
+            *o = from_d2<T2>(nw);
+            // input of the fused diagonal solve: x (forward) or v - acc (backward)
+            if (fz >= 0) sm.xs[c * 64 + r] = TR ? csub(to_d2(vin[(int64_t)(c0 + c) * 64 + r]), nw) : nw;
         }
     }
+    if (fz < 0) return;
+    __syncthreads();
+    vdiag_finish<T2, TR>(dg, blockIdx.y, b, vb, D, nrhs, sm);
 }
 
 // XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
@@ -441,14 +468,18 @@ hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bw
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_vupd(const VUpdTask *tasks, int64_t ntask, const VUpdPair *pairs, int mode, const Bases &b,
-                       const VBases &vb, int nrhs, hipStream_t s) {
+hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
+                       const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
+                       hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
     dim3 grid((unsigned)ntask, (unsigned)((nrhs + SV_COLS - 1) / SV_COLS));
-    if (mode == 0) hipLaunchKernelGGL((vupd_kernel<T2, 0>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
-    else if (mode == 1) hipLaunchKernelGGL((vupd_kernel<T2, 1>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
-    else hipLaunchKernelGGL((vupd_kernel<T2, 2>), grid, dim3(256), 0, s, tasks, pairs, b, vb, nrhs);
+    if (mode == 0)
+        hipLaunchKernelGGL((vupd_kernel<T2, 0>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
+    else if (mode == 1)
+        hipLaunchKernelGGL((vupd_kernel<T2, 1>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
+    else
+        hipLaunchKernelGGL((vupd_kernel<T2, 2>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
     return hipGetLastError();
 }
 template <typename T>
@@ -505,8 +536,9 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
                                          hipStream_t);                                                            \
     template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, int, bool, const Bases &, const VBases &,           \
                                         const DArrays &, int, hipStream_t);                                       \
-    template hipError_t launch_vupd<T>(const VUpdTask *, int64_t, const VUpdPair *, int, const Bases &,            \
-                                       const VBases &, int, hipStream_t);                                         \
+    template hipError_t launch_vupd<T>(const VUpdTask *, const int64_t *, int64_t, const VUpdPair *,            \
+                                       const VDiagTask *, int, const Bases &, const VBases &, const DArrays &, int, \
+                                       hipStream_t);                                         \
     template hipError_t launch_vgather_h<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);     \
     template hipError_t launch_vscatter_lam<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);  \
     template hipError_t launch_vcollect<T>(double2 *, const void *, const int64_t *, int64_t, int, bool,           \
