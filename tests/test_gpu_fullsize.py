@@ -61,3 +61,40 @@ def test_fp32_refinement_reaches_tolerance(cfg2):
     E32, info = s.solve(f, with_info=True)
     assert info["converged"] and info["residual"] <= 1e-10
     assert (torch.linalg.norm(E32 - E64) / torch.linalg.norm(E64)).item() <= 1e-8
+
+
+def test_config5_gradient_vs_central_differences():
+    """Configuration 5 (32^3 hexes, dielectric sphere, 4 right-hand sides):
+    the autograd gradient of L = sum_rhs sum_m |E(r_m)|^2 over the 64
+    receivers, through the adjoint solve, against central differences (each
+    a full factor + solve) on four of the sphere's finite-difference
+    tetrahedra.  The step is h = 1e-4 rather than the configuration's 1e-6:
+    at 1e-6 the rounding of the two FP64 solves (relative residual ~1e-11)
+    divided by 2h already reaches ~1e-4 of these gradients, while the
+    truncation error of a central difference at 1e-4 is O(h^2) ~ 1e-8."""
+    from paper_2002_05018_amd import D3MSolve, Solver
+    prob = W.make_config(5)
+    print("[gpu fullsize] configuration 5", flush=True)
+    s = Solver.from_problem(prob)
+    f = torch.from_numpy(s.rhs_planewave(prob.dirs, prob.pols)).cuda()
+    edges, coef = s.probe(prob.receivers)
+    ed = torch.from_numpy(edges).cuda()
+    cf = torch.from_numpy(coef).cuda().to(torch.complex128)
+
+    def objective(eps):
+        E = D3MSolve.apply(eps, s, f)
+        v = (E[:, ed][..., None] * cf[None]).sum(dim=2)
+        return (v.abs() ** 2).sum()
+
+    eps = torch.tensor(prob.eps_r, dtype=torch.float64, requires_grad=True)
+    L = objective(eps)
+    L.backward()
+    g = eps.grad.numpy()
+    h = 1e-4
+    scale = np.abs(g[prob.learnable]).max()
+    for t in prob.fd_tets[:4]:
+        ep = prob.eps_r.copy(); ep[t] += h
+        em = prob.eps_r.copy(); em[t] -= h
+        with torch.no_grad():
+            fd = (objective(torch.tensor(ep)).item() - objective(torch.tensor(em)).item()) / (2 * h)
+        assert abs(fd - g[t]) <= 1e-4 * max(abs(fd), 1e-2 * scale), (int(t), fd, g[t])
