@@ -478,17 +478,36 @@ bool is_device_ptr(const void *p) {
     return a.type == hipMemoryTypeDevice;
 }
 
-int norms_inf(d3m_problem *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t s) {
-    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
-    if (rc) return rc;
-    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
-    HIPCHK(launch_rownorm_max((unsigned long long *)h->norms.p, v, h->mesh.ne, nrhs, s));
+// per-column infinity norms gathered in h->norms, copied to the host
+int fetch_norms(d3m_problem *h, int nrhs, std::vector<double> &out, hipStream_t s) {
     std::vector<unsigned long long> bits(nrhs);
     HIPCHK(hipMemcpyAsync(bits.data(), h->norms.p, sizeof(unsigned long long) * nrhs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     out.resize(nrhs);
     for (int c = 0; c < nrhs; ++c) std::memcpy(&out[c], &bits[c], sizeof(double));
     return D3M_OK;
+}
+
+int norms_inf(d3m_problem *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t s) {
+    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
+    HIPCHK(launch_rownorm_max((unsigned long long *)h->norms.p, v, h->mesh.ne, nrhs, s));
+    return fetch_norms(h, nrhs, out, s);
+}
+
+// r = f - S E into h->stage_r (FP64) and the per-column infinity norms of r
+int residual_inf(d3m_problem *h, const double2 *f, const double2 *E, int nrhs, std::vector<double> &out,
+                 hipStream_t s) {
+    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
+    hipEvent_t ev{};
+    h->prof_begin(KID_RESID, ev, s);
+    HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs,
+                           (unsigned long long *)h->norms.p, s));
+    h->prof_end(KID_RESID, ev, 0.0, s);
+    return fetch_norms(h, nrhs, out, s);
 }
 
 // full solve on device buffers (both precisions); optional diagnostics
@@ -499,12 +518,8 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         if ((rc = solve_pass<double>(h, f, E, nrhs, false, s))) return rc;
         if (info) {
             if ((rc = h->ensure(h->stage_r, vbytes))) return rc;
-            hipEvent_t ev{};
-            h->prof_begin(KID_RESID, ev, s);
-            HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
-            h->prof_end(KID_RESID, ev, 0.0, s);
             std::vector<double> rn, fn;
-            if ((rc = norms_inf(h, (double2 *)h->stage_r.p, nrhs, rn, s))) return rc;
+            if ((rc = residual_inf(h, f, E, nrhs, rn, s))) return rc;
             if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
             double res = 0.0;
             for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
@@ -526,11 +541,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     double res = 0.0;
     bool ok = false;
     for (;;) {
-        hipEvent_t ev{};
-        h->prof_begin(KID_RESID, ev, s);
-        HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs, s));
-        h->prof_end(KID_RESID, ev, 0.0, s);
-        if ((rc = norms_inf(h, (double2 *)h->stage_r.p, nrhs, rn, s))) return rc;
+        if ((rc = residual_inf(h, f, E, nrhs, rn, s))) return rc;
         res = 0.0;
         for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
         if (res <= h->opt.ir_tol) { ok = true; break; }

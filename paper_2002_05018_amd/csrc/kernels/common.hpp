@@ -48,6 +48,42 @@ __device__ __forceinline__ double2 crecip(double2 z) {
 }
 __device__ __forceinline__ double cabs1(double2 z) { return fabs(z.x) + fabs(z.y); }
 
+
+// Real MFMA products used by the complex tile kernels (4M: four real products
+// per complex one).
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Operand layout of the 16x16x4 products: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Accumulator layout (lane l, register r holds
+// D[row][l % 16]): f64 row = l/16 + 4r, f32 row = 4(l/16) + r.
+template <> struct Mfma<double> {
+    using acc = d4_t;
+    __device__ __forceinline__ static int out_row(int lk, int r) { return lk + 4 * r; }
+    __device__ __forceinline__ static acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<float> {
+    using acc = f4_t;
+    __device__ __forceinline__ static int out_row(int lk, int r) { return 4 * lk + r; }
+    __device__ __forceinline__ static acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// Work-groups are dealt to the 8 XCDs round-robin (group g runs on XCD g % 8),
+// each with its own L2.  Task lists are ordered so that neighbouring tasks
+// share operand tiles (same subdomain and block column), so XCD x is given
+// the contiguous range of tasks [x * per, (x + 1) * per): g -> (g % 8) * per
+// + g / 8.  The grid is 8 * per groups; the few beyond ntask exit at once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_task(int64_t ntask) {
+    const int64_t per = (ntask + kXcds - 1) / kXcds;
+    return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
 template <typename T2> __device__ __forceinline__ T2 *enc_ptr(const Bases &b, int64_t e) {
     return reinterpret_cast<T2 *>(b.p[e >> ENC_SHIFT]) + (e & ENC_MASK);
 }

@@ -552,37 +552,6 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, Base
 // (rows 32*(w>>1), cols 32*(w&1)).  The MFMA's first operand is taken from B
 // and its second from A so that the accumulator holds C^T, whose per-lane
 // layout maps to contiguous runs of column-major C.
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-// Accumulator layout of the 16x16x4 products (lane l, register r holds
-// D[row][l % 16]): f64 row = l/16 + 4r, f32 row = 4(l/16) + r.
-template <> struct Mfma<double> {
-    using acc = d4_t;
-    __device__ __forceinline__ static int out_row(int lk, int r) { return lk + 4 * r; }
-    __device__ __forceinline__ static acc mma(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-};
-template <> struct Mfma<float> {
-    using acc = f4_t;
-    __device__ __forceinline__ static int out_row(int lk, int r) { return 4 * lk + r; }
-    __device__ __forceinline__ static acc mma(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-};
-
-// Work-groups are dealt to the 8 XCDs round-robin (group g runs on XCD g % 8),
-// each with its own L2.  Task lists are ordered so that neighbouring tasks
-// share operand tiles (same subdomain and block column), so XCD x is given
-// the contiguous range of tasks [x * per, (x + 1) * per): g -> (g % 8) * per
-// + g / 8.  The grid is 8 * per groups; the few beyond ntask exit at once.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_task(int64_t ntask) {
-    const int64_t per = (ntask + kXcds - 1) / kXcds;
-    return (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-}
 
 // Accumulates sum_p A_p B_p^T of one task into the per-wave quadrant
 // accumulators (C^T layout, see above).

@@ -58,8 +58,9 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
                            hipStream_t s);
 
 // refinement and adjoint
+// r = f - S E, with max_e |r[c][e]| folded into nmax[c] (zeroed by the caller)
 hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, int64_t ne, int nrhs, hipStream_t s);
+                           const double2 *val, int64_t ne, int nrhs, unsigned long long *nmax, hipStream_t s);
 hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s);
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s);
 hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E, const int64_t *tet_edges,

@@ -1,7 +1,7 @@
 // Solve-phase kernels (recipe steps 6-7 of Section II) and the FP64
 // refinement / adjoint helpers.  Vector tiles hold 64 rows x nrhs columns,
 // column-major (one right-hand side after another), so one 64 x 64 factor
-// tile is applied to every right-hand side while it sits in LDS.
+// tile is applied to many right-hand sides per read.
 #include <type_traits>
 
 #include "common.hpp"
@@ -30,183 +30,157 @@ __global__ void vsplit_kernel(T2 *X, const double2 *f, const int64_t *map, int64
     X[idx] = e >= 0 ? from_d2<T2>(f[(int64_t)c * ne + e]) : T2{0, 0};
 }
 
-// Tile products of the solve sweeps: out (64 x ncol, ncol <= 8 right-hand
-// sides per block) gets op(L) X for 64 x 64 factor tiles L, op = identity
-// or transpose.  Lane r of wave w (4 waves) accumulates row r over the
-// inner indices q in [16 w, 16 w + 16); the four partial sums are added in
-// a fixed order through LDS (results do not depend on timing).  For op =
-// identity each lane reads its 16 entries of L straight from memory (one
-// 1 KB row of lanes per load); for the transpose the tile is staged through
-// LDS (row stride 65) first.  The X block is staged through LDS and read
-// as a broadcast.
-constexpr int SV_COLS = 8;
+// Tile products of the solve sweeps on MFMA: out (64 rows x nc <= 16 NCB
+// right-hand sides) gets op(L) X for 64 x 64 factor tiles L, op = identity or
+// transpose, so that one read of a factor tile serves every right-hand side
+// of the work-group.  The product is formed transposed, out^T = X^T op(L)^T,
+// with 16x16x4 MFMAs (first operand X^T, second op(L)^T; accumulator rows are
+// right-hand sides, columns are output rows).  Wave w owns the output rows
+// m = 16 w + (l % 16) for every column, so no partial sums cross waves.  Lane
+// l holds op(L)(m, q) for the 16 inner indices q = 16 kg + 4 (l / 16) + s
+// (kg, s = 0..3), read straight from memory: for op = identity 16 lanes read
+// one 256-byte run of a column of L, for the transpose each lane reads four
+// consecutive entries of column m.  The X block (inner index x right-hand
+// side) is staged through LDS, column stride SV_PQ (odd, so the 16 columns
+// one read touches fall in distinct banks), double-buffered across the
+// products of one task.
+constexpr int SV_PQ = 65;
 
-template <typename T2, bool TR> struct SolveSmem {
-    double2 ls[TR ? 64 * 65 : 4 * SV_COLS * 64];  // staged tile; reused for the partial sums
-    double2 xs[SV_COLS * 64];                     // X(q, c) at c * 64 + q
+template <typename T2, int NCB> struct SvSmem {
+    T2 xs[2][16 * NCB * SV_PQ];  // X(q, c) at c * SV_PQ + q
 };
 
-// this thread's 16 entries op(L)(r, q), q = 16 w + j
+// lf[4 kg + s] = op(L)(16 w + l % 16, 16 kg + 4 (l / 16) + s)
 template <typename T2, bool TR>
-__device__ __forceinline__ void load_ltile(double (&lx)[16], double (&ly)[16], const T2 *tile, double2 *ls) {
-    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (!TR) {
+__device__ __forceinline__ void sv_load_l(T2 (&lf)[16], const T2 *tile) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int m = 16 * (threadIdx.x >> 6) + li;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const T2 v = tile[(16 * w + j) * 64 + r];
-            lx[j] = v.x;
-            ly[j] = v.y;
+    for (int kg = 0; kg < 4; ++kg)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int q = 16 * kg + 4 * lk + s;
+            lf[4 * kg + s] = TR ? tile[m * 64 + q] : tile[q * 64 + m];
         }
-    } else {
-        // stage: element e of the column-major tile is L(e & 63, e >> 6)
-        T2 v[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = tile[threadIdx.x + 256 * i];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            ls[(e >> 6) * 65 + (e & 63)] = to_d2(v[i]);
-        }
-        __syncthreads();
-        // L^T(r, q) = L(q, r) at ls[r * 65 + q]
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double2 u = ls[r * 65 + 16 * w + j];
-            lx[j] = u.x;
-            ly[j] = u.y;
-        }
-    }
 }
 
-// X block (columns c0 .. c0 + ncol - 1 of a vector tile, minus sub) into xs
-template <typename T2>
-__device__ __forceinline__ void stage_x(double2 *xs, const T2 *src, const T2 *sub, int c0, int ncol) {
-    double2 v[2];
+// this thread's share of the X block: columns c0 .. c0 + ncol - 1 of a vector
+// tile, minus the same columns of sub (if given); zero beyond ncol
+template <typename T2, int NCB>
+__device__ __forceinline__ void sv_fetch_x(T2 (&xr)[4 * NCB], const T2 *src, const T2 *sub, int c0, int ncol) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4 * NCB; ++i) {
         const int e = threadIdx.x + 256 * i;
-        v[i] = make_double2(0, 0);
-        if (e < 64 * ncol) {
-            v[i] = to_d2(src[(int64_t)c0 * 64 + e]);
-            if (sub) v[i] = csub(v[i], to_d2(sub[(int64_t)c0 * 64 + e]));
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int e = threadIdx.x + 256 * i;
-        if (e < 64 * ncol) xs[e] = v[i];
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void tile_fma(double (&ax)[SV_COLS], double (&ay)[SV_COLS], const double (&lx)[16],
-                                         const double (&ly)[16], const double2 *xs, int ncol) {
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int q = 16 * w + j;
-#pragma unroll
-        for (int c = 0; c < SV_COLS; ++c) {
-            if (c < ncol) {
-                const double2 x = xs[c * 64 + q];
-                ax[c] = fma(lx[j], x.x, fma(-ly[j], x.y, ax[c]));
-                ay[c] = fma(lx[j], x.y, fma(ly[j], x.x, ay[c]));
+        T2 v{0, 0};
+        if ((e >> 6) < ncol) {
+            v = src[(int64_t)c0 * 64 + e];
+            if (sub) {
+                const T2 u = sub[(int64_t)c0 * 64 + e];
+                v = T2{v.x - u.x, v.y - u.y};
             }
         }
+        xr[i] = v;
+    }
+}
+template <typename T2, int NCB> __device__ __forceinline__ void sv_put_x(T2 *xs, const T2 (&xr)[4 * NCB]) {
+#pragma unroll
+    for (int i = 0; i < 4 * NCB; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        xs[(e >> 6) * SV_PQ + (e & 63)] = xr[i];
     }
 }
 
-// sum of the four waves' partials for (row r, column c) in a fixed order;
-// thread (r, w) finishes columns w and w + 4
-__device__ __forceinline__ void reduce_partials(double2 *red, const double (&ax)[SV_COLS], const double (&ay)[SV_COLS],
-                                                double2 (&res)[2]) {
-    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
+// acc += (op(L) X)^T for the fragment lf and the staged block xs
+template <typename T, int NCB>
+__device__ __forceinline__ void sv_mma(typename Mfma<T>::acc (&re)[NCB], typename Mfma<T>::acc (&im)[NCB],
+                                       const typename C2T<T>::type (&lf)[16], const typename C2T<T>::type *xs) {
+    using M = Mfma<T>;
+    using T2 = typename C2T<T>::type;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int c = 0; c < SV_COLS; ++c) red[(w * SV_COLS + c) * 64 + r] = make_double2(ax[c], ay[c]);
-    __syncthreads();
+    for (int kg = 0; kg < 4; ++kg)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int c = w + 4 * h;
-        double2 s = red[(0 * SV_COLS + c) * 64 + r];
-        s = cadd(s, red[(1 * SV_COLS + c) * 64 + r]);
-        s = cadd(s, red[(2 * SV_COLS + c) * 64 + r]);
-        s = cadd(s, red[(3 * SV_COLS + c) * 64 + r]);
-        res[h] = s;
-    }
+        for (int s = 0; s < 4; ++s) {
+            const int q = 16 * kg + 4 * lk + s;
+            const T2 bl = lf[4 * kg + s];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const T2 ax = xs[(16 * cb + li) * SV_PQ + q];
+                re[cb] = M::mma(ax.x, bl.x, re[cb]);
+                im[cb] = M::mma(ax.x, bl.y, im[cb]);
+                re[cb] = M::mma(-ax.y, bl.y, re[cb]);
+                im[cb] = M::mma(ax.y, bl.x, im[cb]);
+            }
+        }
 }
 
-// Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y.
-// Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
-// Blocks of one tile (n <= 64); chunk selects 8 right-hand sides.
-// vdiag_finish applies TT (or TT^T) to the block already staged in sm.xs and
-// writes the outputs.
-template <typename T2, bool BWD, typename Smem>
-__device__ __forceinline__ void vdiag_finish(const VDiagTask &tk, int chunk, const Bases &b, const VBases &vb,
-                                             const DArrays &D, int nrhs, Smem &sm) {
-    const int c0 = chunk * SV_COLS;
-    const int ncol = min(SV_COLS, nrhs - c0);
-    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double lx[16], ly[16], ax[SV_COLS], ay[SV_COLS];
+// Diagonal solve of a one-tile block from the input staged in xin.
+// Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y (2x2 pivots
+// never cross the tile).  Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
+// xsp is a free LDS buffer.
+template <typename T, bool BWD, int NCB>
+__device__ __forceinline__ void sv_diag(const VDiagTask &tk, int c0, int ncol, const Bases &b, const VBases &vb,
+                                        const DArrays &D, int nrhs, const typename C2T<T>::type *xin,
+                                        typename C2T<T>::type *xsp) {
+    using M = Mfma<T>;
+    using T2 = typename C2T<T>::type;
+    using acc_t = typename M::acc;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int m = 16 * (threadIdx.x >> 6) + li;
+    T2 lf[16];
+    sv_load_l<T2, BWD>(lf, enc_ptr<T2>(b, tk.tt));
+    acc_t re[NCB], im[NCB];
 #pragma unroll
-    for (int c = 0; c < SV_COLS; ++c) ax[c] = ay[c] = 0.0;
-    load_ltile<T2, BWD>(lx, ly, enc_ptr<T2>(b, tk.tt), sm.ls);
-    tile_fma(ax, ay, lx, ly, sm.xs, ncol);
-    double2 res[2];
-    reduce_partials(sm.ls, ax, ay, res);
-    if (BWD) {
-        T2 *x = vptr<T2>(vb, tk.x, nrhs);
+    for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
+    sv_mma<T, NCB>(re, im, lf, xin);
+    T2 *out = vptr<T2>(vb, BWD ? tk.x : tk.y, nrhs) + (int64_t)c0 * 64;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = w + 4 * h;
-            if (c < ncol) x[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(res[h]);
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * cb + M::out_row(lk, r);
+            if (c < ncol) out[c * 64 + m] = T2{re[cb][r], im[cb][r]};
+            if (!BWD) xsp[c * SV_PQ + m] = T2{re[cb][r], im[cb][r]};
         }
-        return;
-    }
-    // v = D^{-1} y within the tile (2x2 pivots never cross it); y goes through xs
-    T2 *y = vptr<T2>(vb, tk.y, nrhs);
+    if (BWD) return;
     __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int c = w + 4 * h;
-        if (c < ncol) {
-            sm.xs[c * 64 + r] = res[h];
-            y[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(res[h]);
-        }
-    }
-    __syncthreads();
-    T2 *v = vptr<T2>(vb, tk.v, nrhs);
-    const int64_t dr = tk.drow + r;
-    const bool live = r < tk.n;
+    T2 *v = vptr<T2>(vb, tk.v, nrhs) + (int64_t)c0 * 64;
+    const int64_t dr = tk.drow + m;
+    const bool live = m < tk.n;
     const double2 di = live ? D.dinv[dr] : make_double2(0, 0);
     const int pv = live ? D.piv[dr] : 0;
     const double2 dio = pv ? D.dinvoff[dr] : make_double2(0, 0);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int c = w + 4 * h;
-        if (c < ncol) {
-            double2 val = cmul(di, sm.xs[c * 64 + r]);
-            if (pv != 0) val = cadd(val, cmul(dio, sm.xs[c * 64 + r + pv]));
-            v[(int64_t)(c0 + c) * 64 + r] = from_d2<T2>(live ? val : make_double2(0, 0));
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * cb + M::out_row(lk, r);
+            if (c < ncol) {
+                double2 val = cmul(di, to_d2(xsp[c * SV_PQ + m]));
+                if (pv != 0) val = cadd(val, cmul(dio, to_d2(xsp[c * SV_PQ + m + pv])));
+                v[c * 64 + m] = from_d2<T2>(live ? val : make_double2(0, 0));
+            }
         }
-    }
 }
 
-template <typename T2, bool BWD>
-__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, Bases b, VBases vb, DArrays D, int nrhs) {
-    __shared__ SolveSmem<T2, BWD> sm;
-    const VDiagTask tk = tasks[blockIdx.x];
-    const int c0 = blockIdx.y * SV_COLS;
-    const int ncol = min(SV_COLS, nrhs - c0);
-    if (BWD) {
-        const T2 *accv = tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr;
-        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.v, nrhs), accv, c0, ncol);
-    } else {
-        stage_x<T2>(sm.xs, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
-    }
-    vdiag_finish<T2, BWD>(tk, blockIdx.y, b, vb, D, nrhs, sm);
+template <typename T, bool BWD, int NCB>
+__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int64_t ntask, Bases b, VBases vb,
+                                                    DArrays D, int nrhs) {
+    using T2 = typename C2T<T>::type;
+    __shared__ SvSmem<T2, NCB> sm;
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const VDiagTask tk = tasks[task];
+    const int c0 = blockIdx.y * 16 * NCB;
+    const int ncol = min(16 * NCB, nrhs - c0);
+    T2 xr[4 * NCB];
+    if (BWD)
+        sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.v, nrhs), tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr, c0, ncol);
+    else
+        sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
+    sv_put_x<T2, NCB>(sm.xs[0], xr);
+    __syncthreads();
+    sv_diag<T, BWD, NCB>(tk, c0, ncol, b, vb, D, nrhs, sm.xs[0], sm.xs[1]);
 }
 
 // Diagonal blocks of several tiles (blocks larger than 64 factored whole):
@@ -295,57 +269,84 @@ __global__ __launch_bounds__(256) void vdiag_multi_kernel(const VDiagTask *tasks
 }
 
 // out (-=|=|+=) sum_p op(L_p) src_p with op = identity (mode 0) or
-// transpose (modes 1, 2); blockIdx.y selects 8 right-hand sides.  When
-// fuse[task] >= 0 this update is the last one its target receives before the
-// diagonal solve fuse[task] (forward: the target is that block's x; backward:
-// its accumulator), so the work-group goes on with that solve from the new
-// values kept in LDS, saving a launch per sweep step.
-template <typename T2, int MODE>
-__global__ __launch_bounds__(256) void vupd_kernel(const VUpdTask *tasks, const int64_t *fuse, const VUpdPair *pairs,
-                                                   const VDiagTask *vdiag, Bases b, VBases vb, DArrays D, int nrhs) {
+// transpose (modes 1, 2); blockIdx.y selects 16 NCB right-hand sides.  The
+// factor tile and X block of product p + 1 are fetched while product p runs.
+// When fuse[task] >= 0 this update is the last one its target receives before
+// the diagonal solve fuse[task] (forward: the target is that block's x;
+// backward: its accumulator), so the work-group goes on with that solve from
+// the new values kept in LDS, saving a launch per sweep step.
+template <typename T, int MODE, int NCB>
+__global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask,
+                                                   const VUpdPair *pairs, const VDiagTask *vdiag, Bases b, VBases vb,
+                                                   DArrays D, int nrhs) {
+    using M = Mfma<T>;
+    using T2 = typename C2T<T>::type;
+    using acc_t = typename M::acc;
     constexpr bool TR = MODE != 0;
-    __shared__ SolveSmem<T2, TR> sm;
-    const VUpdTask tk = tasks[blockIdx.x];
-    const int64_t fz = fuse[blockIdx.x];
-    const int c0 = blockIdx.y * SV_COLS;
-    const int ncol = min(SV_COLS, nrhs - c0);
-    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double ax[SV_COLS], ay[SV_COLS];
+    __shared__ SvSmem<T2, NCB> sm;
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const VUpdTask tk = tasks[task];
+    const int64_t fz = fuse[task];
+    const int c0 = blockIdx.y * 16 * NCB;
+    const int ncol = min(16 * NCB, nrhs - c0);
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int m = 16 * (threadIdx.x >> 6) + li;
+    acc_t re[NCB], im[NCB];
 #pragma unroll
-    for (int c = 0; c < SV_COLS; ++c) ax[c] = ay[c] = 0.0;
-    for (int p = 0; p < tk.np; ++p) {
-        const VUpdPair pr = pairs[tk.p0 + p];
-        double lx[16], ly[16];
-        load_ltile<T2, TR>(lx, ly, enc_ptr<T2>(b, pr.l), sm.ls);
-        stage_x<T2>(sm.xs, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
-        tile_fma(ax, ay, lx, ly, sm.xs, ncol);
+    for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
+    T2 lf[16], xr[4 * NCB];
+    if (tk.np > 0) {
+        const VUpdPair pr = pairs[tk.p0];
+        sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
+        sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
     }
-    double2 res[2];
-    reduce_partials(sm.ls, ax, ay, res);
-    T2 *out = vptr<T2>(vb, tk.out, nrhs);
+    for (int p = 0; p < tk.np; ++p) {
+        T2 *xs = sm.xs[p & 1];
+        sv_put_x<T2, NCB>(xs, xr);
+        __syncthreads();
+        T2 lc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) lc[j] = lf[j];
+        if (p + 1 < tk.np) {
+            const VUpdPair pr = pairs[tk.p0 + p + 1];
+            sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
+            sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
+        }
+        sv_mma<T, NCB>(re, im, lc, xs);
+    }
+    T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
     VDiagTask dg{};
     const T2 *vin = nullptr;
     if (fz >= 0) {
         dg = vdiag[fz];
-        if (TR) vin = vptr<T2>(vb, dg.v, nrhs);
+        if (TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
     }
+    // the buffer not read by the last product (its previous readers passed the last barrier)
+    T2 *xd = sm.xs[tk.np & 1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int c = w + 4 * h;
-        if (c < ncol) {
-            T2 *o = out + (int64_t)(c0 + c) * 64 + r;
-            double2 nw;
-            if (MODE == 0) nw = csub(to_d2(*o), res[h]);
-            else if (MODE == 1) nw = res[h];
-            else nw = cadd(to_d2(*o), res[h]);
-            *o = from_d2<T2>(nw);
-            // input of the fused diagonal solve: x (forward) or v - acc (backward)
-            if (fz >= 0) sm.xs[c * 64 + r] = TR ? csub(to_d2(vin[(int64_t)(c0 + c) * 64 + r]), nw) : nw;
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * cb + M::out_row(lk, r);
+            T2 nw{0, 0};
+            if (c < ncol) {
+                T2 *o = out + c * 64 + m;
+                if (MODE == 0) nw = T2{(*o).x - re[cb][r], (*o).y - im[cb][r]};
+                else if (MODE == 1) nw = T2{re[cb][r], im[cb][r]};
+                else nw = T2{(*o).x + re[cb][r], (*o).y + im[cb][r]};
+                *o = nw;
+                // input of the fused diagonal solve: x (forward) or v - acc (backward)
+                if (TR && fz >= 0) {
+                    const T2 vv = vin[c * 64 + m];
+                    nw = T2{vv.x - nw.x, vv.y - nw.y};
+                }
+            }
+            if (fz >= 0) xd[c * SV_PQ + m] = nw;
         }
-    }
     if (fz < 0) return;
     __syncthreads();
-    vdiag_finish<T2, TR>(dg, blockIdx.y, b, vb, D, nrhs, sm);
+    sv_diag<T, TR, NCB>(dg, c0, ncol, b, vb, D, nrhs, xd, sm.xs[(tk.np + 1) & 1]);
 }
 
 // XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
@@ -387,16 +388,45 @@ __global__ void vcollect_kernel(double2 *E, const T2 *X, const int64_t *cmap, in
     E[idx] = ACC ? cadd(E[idx], v) : v;
 }
 
-// r = f - S E (CSR of the global FEM matrix, FP64)
-__global__ void residual_kernel(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr,
-                                const int32_t *col, const double2 *val, int64_t ne, int nrhs) {
-    int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= ne) return;
-    for (int c = 0; c < nrhs; ++c) {
-        double2 s = f[(int64_t)c * ne + row];
-        const double2 *Ec = E + (int64_t)c * ne;
-        for (int64_t k = rowptr[row]; k < rowptr[row + 1]; ++k) s = cfms(s, val[k], Ec[col[k]]);
-        r[(int64_t)c * ne + row] = s;
+// r = f - S E (CSR of the global FEM matrix, FP64).  One thread per row and
+// RES_COLS right-hand sides (blockIdx.y selects them): the row's entries are
+// read once for all of them, and the gathers of E for one entry are
+// independent of each other.  nmax[c] (zeroed by the caller) gets
+// max_e |r[c][e]| (modulus) as the bit pattern of a non-negative double
+// (monotone under unsigned comparison).
+constexpr int RES_COLS = 16;
+
+__global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *E,
+                                                       const int64_t *rowptr, const int32_t *col, const double2 *val,
+                                                       int64_t ne, int nrhs, unsigned long long *nmax) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c0 = blockIdx.y * RES_COLS;
+    const int nc = min(RES_COLS, nrhs - c0);
+    const bool live = row < ne;
+    double2 s[RES_COLS];
+#pragma unroll
+    for (int c = 0; c < RES_COLS; ++c) s[c] = make_double2(0, 0);
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < RES_COLS; ++c)
+            if (c < nc) s[c] = f[(int64_t)(c0 + c) * ne + row];
+        const int64_t k1 = rowptr[row + 1];
+        for (int64_t k = rowptr[row]; k < k1; ++k) {
+            const double2 v = val[k];
+            const double2 *Ek = E + (int64_t)c0 * ne + col[k];
+#pragma unroll
+            for (int c = 0; c < RES_COLS; ++c)
+                if (c < nc) s[c] = cfms(s[c], v, Ek[(int64_t)c * ne]);
+        }
+#pragma unroll
+        for (int c = 0; c < RES_COLS; ++c)
+            if (c < nc) r[(int64_t)(c0 + c) * ne + row] = s[c];
+    }
+#pragma unroll
+    for (int c = 0; c < RES_COLS; ++c) {
+        double m = sqrt(s[c].x * s[c].x + s[c].y * s[c].y);
+        for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0 && c < nc) atomicMax(&nmax[c0 + c], (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -451,15 +481,25 @@ hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t 
     hipLaunchKernelGGL(vsplit_kernel<T2>, g1(nrows * nrhs), dim3(256), 0, s, (T2 *)X, f, map, nrows, nrhs, ne);
     return hipGetLastError();
 }
+// right-hand sides per work-group: 16 (one MFMA column block) or 32
+inline int sv_ncb(int nrhs) { return nrhs <= 16 ? 1 : 2; }
+inline unsigned sv_groups(int64_t ntask) { return (unsigned)(((ntask + kXcds - 1) / kXcds) * kXcds); }
+
 template <typename T>
 hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
                         const DArrays &D, int nrhs, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
     if (maxt <= 1) {
-        dim3 grid((unsigned)ntask, (unsigned)((nrhs + SV_COLS - 1) / SV_COLS));
-        if (bwd) hipLaunchKernelGGL((vdiag_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
-        else hipLaunchKernelGGL((vdiag_kernel<T2, false>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
+        const int ncb = sv_ncb(nrhs);
+        dim3 grid(sv_groups(ntask), (unsigned)((nrhs + 16 * ncb - 1) / (16 * ncb)));
+        if (ncb == 1) {
+            if (bwd) hipLaunchKernelGGL((vdiag_kernel<T, true, 1>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
+            else hipLaunchKernelGGL((vdiag_kernel<T, false, 1>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
+        } else {
+            if (bwd) hipLaunchKernelGGL((vdiag_kernel<T, true, 2>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
+            else hipLaunchKernelGGL((vdiag_kernel<T, false, 2>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
+        }
     } else {
         dim3 grid((unsigned)ntask, (unsigned)((nrhs + 31) / 32));
         if (bwd) hipLaunchKernelGGL((vdiag_multi_kernel<T2, true>), grid, dim3(256), 0, s, tasks, b, vb, D, nrhs);
@@ -467,19 +507,29 @@ hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bw
     }
     return hipGetLastError();
 }
+
+template <typename T, int NCB>
+void launch_vupd_ncb(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
+                     const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
+                     hipStream_t s) {
+    dim3 grid(sv_groups(ntask), (unsigned)((nrhs + 16 * NCB - 1) / (16 * NCB)));
+    if (mode == 0)
+        hipLaunchKernelGGL((vupd_kernel<T, 0, NCB>), grid, dim3(256), 0, s, tasks, fuse, ntask, pairs, vdiag, b, vb, D,
+                           nrhs);
+    else if (mode == 1)
+        hipLaunchKernelGGL((vupd_kernel<T, 1, NCB>), grid, dim3(256), 0, s, tasks, fuse, ntask, pairs, vdiag, b, vb, D,
+                           nrhs);
+    else
+        hipLaunchKernelGGL((vupd_kernel<T, 2, NCB>), grid, dim3(256), 0, s, tasks, fuse, ntask, pairs, vdiag, b, vb, D,
+                           nrhs);
+}
 template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                        const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
                        hipStream_t s) {
-    using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
-    dim3 grid((unsigned)ntask, (unsigned)((nrhs + SV_COLS - 1) / SV_COLS));
-    if (mode == 0)
-        hipLaunchKernelGGL((vupd_kernel<T2, 0>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
-    else if (mode == 1)
-        hipLaunchKernelGGL((vupd_kernel<T2, 1>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
-    else
-        hipLaunchKernelGGL((vupd_kernel<T2, 2>), grid, dim3(256), 0, s, tasks, fuse, pairs, vdiag, b, vb, D, nrhs);
+    if (sv_ncb(nrhs) == 1) launch_vupd_ncb<T, 1>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
+    else launch_vupd_ncb<T, 2>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
     return hipGetLastError();
 }
 template <typename T>
@@ -510,8 +560,9 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
 }
 
 hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, int64_t ne, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(residual_kernel, g1(ne), dim3(256), 0, s, r, f, E, rowptr, col, val, ne, nrhs);
+                           const double2 *val, int64_t ne, int nrhs, unsigned long long *nmax, hipStream_t s) {
+    dim3 grid(g1(ne).x, (unsigned)((nrhs + RES_COLS - 1) / RES_COLS));
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, r, f, E, rowptr, col, val, ne, nrhs, nmax);
     return hipGetLastError();
 }
 hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s) {
