@@ -81,7 +81,14 @@ typedef struct {
                              overhead; 2 adds about a tenth at config 2)      */
     double ir_tol;        /* FP32_IR: stop when max over right-hand sides of
                              ||f - S E||_inf / ||f||_inf <= ir_tol (1e-10)   */
-    int32_t use_graph;    /* reserved (0)                                     */
+    int32_t use_graph;    /* 1: d3m_factor captures its launch sequence into a
+                             HIP graph on first use (per precision) and
+                             replays it; d3m_solve does the same per
+                             (precision, rhs and E buffers, nrhs), keeping at
+                             most 8 solve graphs.  Graphs run on a stream of
+                             the handle, ordered after the work already on
+                             the caller's stream and before its later work.
+                             Profiling events are not recorded in graphs.   */
     int32_t device;       /* HIP device ordinal (default 0)                   */
     int32_t pivot_scope;  /* Bunch-Kaufman pivot search of step 5 restricted
                              to: 0 (default) consecutive pieces of at most 64
@@ -113,7 +120,10 @@ typedef struct {
     int32_t factored;         /* 0 none, else D3M_FP64 + 1 or D3M_FP32_IR + 1 */
     int32_t n_units;          /* pivot units of K (blocks or pieces of blocks) */
     int32_t n_unit_levels;    /* elimination-tree levels over the units       */
-    int32_t reserved[5];
+    int32_t n_problems;       /* independent problems held (1 unless batched) */
+    int64_t array_bytes;      /* device bytes of the factor arrays of one
+                                 precision (complex128; half for FP32_IR)     */
+    int32_t reserved[2];
 } d3m_info;
 
 typedef struct {
@@ -141,6 +151,34 @@ void d3m_default_options(d3m_options *opt);
  * connected through shared triangles), D3M_ENOMEM, D3M_ENODEV, D3M_EHIP. */
 int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r,
               double k, d3m_c128 alpha, const d3m_options *opt, d3m_handle *out);
+
+/* One problem of a batch: its mesh, partition (ids dense in [0, N_p)) and
+ * eps_r, with the same meaning as the arguments of d3m_setup. */
+typedef struct {
+    d3m_mesh mesh;
+    const int32_t *part;
+    const double *eps_r;
+} d3m_batch_item;
+
+/* Batch of `count` independent problems at one wavenumber k and Robin
+ * coefficient alpha (Section II applied to each problem; the problems share
+ * no unknowns, so their systems do not couple).  The handle holds their
+ * disjoint union: every phase runs over the subdomains of all problems at
+ * once (uneven subdomain sizes included) and the block elimination tree of
+ * K is a forest with one nested-dissection tree per problem.  Edges and
+ * tetrahedra of problem p are the contiguous ranges [edge_off[p],
+ * edge_off[p+1]) and [tet_off[p], tet_off[p+1]) of the handle's numbering
+ * (d3m_batch_layout), in each problem's own order, so a right-hand side or
+ * solution of the batch is [nrhs][sum of n_edges] with problem p's columns
+ * in its range.  The refinement tolerance of FP32_IR holds for every problem
+ * and right-hand side separately.  Errors as for d3m_setup. */
+int d3m_setup_batch(const d3m_batch_item *items, int32_t count, double k,
+                    d3m_c128 alpha, const d3m_options *opt, d3m_handle *out);
+
+/* Number of problems and the offsets above ([count + 1] each; any output
+ * pointer may be NULL).  A handle from d3m_setup holds one problem. */
+int d3m_batch_layout(d3m_handle h, int32_t *count, int64_t *edge_off,
+                     int64_t *tet_off);
 
 /* Replace eps_r ([n_tets], copied), reassemble the subdomain matrices and
  * invalidate the factors.  Errors: D3M_EINVAL, D3M_EHIP. */
@@ -182,16 +220,42 @@ int d3m_adjoint(d3m_handle h, const d3m_c128 *grad_E, const d3m_c128 *E,
 int d3m_rhs_planewave(d3m_handle h, const double *dirs, const double *pols,
                       int32_t nrhs, d3m_c128 *f);
 
+/* d3m_rhs_planewave with its own waves per problem of a batch:
+ *   dirs, pols [count][nrhs][3]; f [nrhs][n_edges] host output. */
+int d3m_rhs_planewave_batch(d3m_handle h, const double *dirs,
+                            const double *pols, int32_t nrhs, d3m_c128 *f);
+
 /* Whitney field evaluation at points: for point m, E(r_m) = sum_a c[m][a][:] *
  * u[edge[m][a]] over the six edges of the tetrahedron containing r_m.
  *   pts [n][3]; edges [n][6] (int64) and coef [n][6][3] (double) host outputs.
- * Errors: D3M_EINVAL when a point lies outside the mesh. */
+ * Errors: D3M_EINVAL when a point lies outside the mesh or the handle holds
+ * a batch. */
 int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges,
               double *coef);
 
 int d3m_query(d3m_handle h, d3m_info *info);
 void d3m_destroy(d3m_handle h);
 const char *d3m_last_error(void);
+
+/* Launch-shape choices of the schedules; paper_2002_05018_amd.autotune picks
+ * them by timing.  Zero selects the default. */
+typedef struct {
+    int32_t s1_block;        /* tile columns of a subdomain matrix whose Schur
+                                updates beyond them are applied together
+                                (d3m_options.s1_block; default 2, at most 16) */
+    int32_t solve_cols;      /* right-hand sides per work-group of the solve
+                                sweeps: 16 or 32 (default 32)                 */
+    int32_t lookahead_tasks; /* an elimination step whose updates off the
+                                next step's columns number at least this many
+                                tasks runs them on a second stream (512)     */
+    int32_t reserved[5];
+} d3m_tuning;
+
+/* Read / replace the tuning.  A new s1_block rebuilds the factor schedule
+ * (the storage layout is unchanged) and invalidates the factors; any change
+ * drops captured graphs.  Errors: D3M_EINVAL (value out of range). */
+int d3m_get_tuning(d3m_handle h, d3m_tuning *t);
+int d3m_set_tuning(d3m_handle h, const d3m_tuning *t);
 
 /* Change the profiling level of opt.profile (0, 1 or 2) for later calls.
  * Returns D3M_EINVAL for another level or a null handle. */

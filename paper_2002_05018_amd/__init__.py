@@ -11,6 +11,7 @@ fails.
 from ._lib import (D3MError, Solver, FP64, FP32_IR, KERNEL_IDS, library_path,
                    exported_symbols)
 from .autograd import D3MSolve
+from .autotune import autotune
 
-__all__ = ["D3MError", "Solver", "FP64", "FP32_IR", "KERNEL_IDS", "D3MSolve",
+__all__ = ["D3MError", "Solver", "FP64", "FP32_IR", "KERNEL_IDS", "D3MSolve", "autotune",
            "library_path", "exported_symbols"]

@@ -13,6 +13,16 @@ if not os.path.exists(library_path):
     raise ImportError(f"{library_path} is missing: build it with "
                       "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
 
+# The library and PyTorch exchange device pointers and streams, so the
+# process must hold one HIP runtime.  PyTorch ships its own libamdhip64.so.7
+# (same soname as the system one the library links): importing torch first
+# loads PyTorch's, and the library's dependency then resolves to it.  Loading
+# the library first would bind PyTorch to the other runtime instead.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # host-only use without PyTorch
+    _torch = None
+
 _lib = C.CDLL(library_path)
 
 FP64 = 0
@@ -30,7 +40,8 @@ EXPORT = {"edges": 1, "sub_edges": 2, "sub_ni": 3, "a_coo": 4, "lms": 5, "order"
 exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_factor",
                     "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
-                    "d3m_debug_export"]
+                    "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
+                    "d3m_get_tuning", "d3m_set_tuning"]
 
 
 class d3m_c128(C.Structure):
@@ -56,6 +67,15 @@ class d3m_info(C.Structure):
                 ("flops_domain", C.c_double), ("flops_block_ldlt", C.c_double),
                 ("flops_update_gemm", C.c_double), ("solve_bytes", C.c_double),
                 ("factored", C.c_int32), ("n_units", C.c_int32), ("n_unit_levels", C.c_int32),
+                ("n_problems", C.c_int32), ("array_bytes", C.c_int64), ("reserved", C.c_int32 * 2)]
+
+
+class d3m_batch_item(C.Structure):
+    _fields_ = [("mesh", d3m_mesh), ("part", C.POINTER(C.c_int32)), ("eps_r", C.POINTER(C.c_double))]
+
+
+class d3m_tuning(C.Structure):
+    _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
                 ("reserved", C.c_int32 * 5)]
 
 
@@ -69,6 +89,13 @@ _lib.d3m_default_options.argtypes = [C.POINTER(d3m_options)]
 _lib.d3m_default_options.restype = None
 _lib.d3m_setup.argtypes = [C.POINTER(d3m_mesh), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                            C.c_double, d3m_c128, C.POINTER(d3m_options), C.POINTER(_h)]
+_lib.d3m_setup_batch.argtypes = [C.POINTER(d3m_batch_item), C.c_int32, C.c_double, d3m_c128,
+                                 C.POINTER(d3m_options), C.POINTER(_h)]
+_lib.d3m_batch_layout.argtypes = [_h, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+_lib.d3m_rhs_planewave_batch.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                         C.c_void_p]
+_lib.d3m_get_tuning.argtypes = [_h, C.POINTER(d3m_tuning)]
+_lib.d3m_set_tuning.argtypes = [_h, C.POINTER(d3m_tuning)]
 _lib.d3m_update_eps.argtypes = [_h, C.POINTER(C.c_double)]
 _lib.d3m_factor.argtypes = [_h, C.c_int, C.c_void_p]
 _lib.d3m_solve.argtypes = [_h, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(d3m_solve_info), C.c_void_p]
@@ -84,8 +111,9 @@ _lib.d3m_kernel_stats.argtypes = [_h, C.c_int, C.c_int, C.POINTER(C.c_int64), C.
 _lib.d3m_debug_export.argtypes = [_h, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
 _lib.d3m_debug_export.restype = C.c_int64
 _lib.d3m_set_profile.argtypes = [_h, C.c_int]
-for _f in ("d3m_setup", "d3m_update_eps", "d3m_factor", "d3m_solve", "d3m_adjoint",
-           "d3m_rhs_planewave", "d3m_probe", "d3m_query", "d3m_set_profile", "d3m_kernel_stats"):
+for _f in ("d3m_setup", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch", "d3m_update_eps",
+           "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
+           "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -115,35 +143,68 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-class Solver:
-    """One decomposed problem on the GPU (a d3m_handle)."""
+def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10,
+             pivot_scope=0, s1_block=0, use_graph=False):
+    opt = d3m_options()
+    _lib.d3m_default_options(C.byref(opt))
+    opt.host_only = int(host_only)
+    # True: every kernel group; an int: that level (0 off, 1 update GEMMs, 2 all)
+    opt.profile = 2 if profile is True else int(profile)
+    opt.device = int(device)
+    opt.quad_points = int(quad_points)
+    opt.ir_tol = float(ir_tol)
+    opt.ir_max_iter = int(ir_max_iter)
+    opt.pivot_scope = int(pivot_scope)
+    opt.s1_block = int(s1_block)
+    opt.use_graph = int(use_graph)
+    return opt
 
-    def __init__(self, xyz, tets, part, eps_r, k, alpha, *, host_only=False, profile=False,
-                 device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10, pivot_scope=0, s1_block=0):
-        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
-        self._tets = np.ascontiguousarray(tets, dtype=np.int64)
-        self._part = np.ascontiguousarray(part, dtype=np.int32)
+
+class Solver:
+    """One decomposed problem, or a batch of independent ones, on the GPU (a
+    d3m_handle)."""
+
+    def __init__(self, xyz, tets, part, eps_r, k, alpha, **kw):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int64)
+        part = np.ascontiguousarray(part, dtype=np.int32)
         eps = np.ascontiguousarray(eps_r, dtype=np.float64)
-        mesh = d3m_mesh(self._xyz.shape[0], _ptr(self._xyz, C.c_double), self._tets.shape[0],
-                        _ptr(self._tets, C.c_int64))
-        opt = d3m_options()
-        _lib.d3m_default_options(C.byref(opt))
-        opt.host_only = int(host_only)
-        # True: every kernel group; an int: that level (0 off, 1 update GEMMs, 2 all)
-        opt.profile = 2 if profile is True else int(profile)
-        opt.device = int(device)
-        opt.quad_points = int(quad_points)
-        opt.ir_tol = float(ir_tol)
-        opt.ir_max_iter = int(ir_max_iter)
-        opt.pivot_scope = int(pivot_scope)
-        opt.s1_block = int(s1_block)
+        mesh = d3m_mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int64))
+        opt = _options(**kw)
         a = complex(alpha)
         h = _h()
-        _check(_lib.d3m_setup(C.byref(mesh), _ptr(self._part, C.c_int32), _ptr(eps, C.c_double),
+        _check(_lib.d3m_setup(C.byref(mesh), _ptr(part, C.c_int32), _ptr(eps, C.c_double),
                               float(k), d3m_c128(a.real, a.imag), C.byref(opt), C.byref(h)))
+        self._adopt(h, k, opt)
+
+    @classmethod
+    def batch(cls, problems, k, alpha, **kw):
+        """One handle over independent problems (d3m_setup_batch).  problems:
+        sequence of objects with xyz, tets, part and eps_r (e.g. Problem)."""
+        keep = []
+        items = (d3m_batch_item * len(problems))()
+        for i, p in enumerate(problems):
+            xyz = np.ascontiguousarray(p.xyz, dtype=np.float64)
+            tets = np.ascontiguousarray(p.tets, dtype=np.int64)
+            part = np.ascontiguousarray(p.part, dtype=np.int32)
+            eps = np.ascontiguousarray(p.eps_r, dtype=np.float64)
+            keep += [xyz, tets, part, eps]
+            items[i].mesh = d3m_mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int64))
+            items[i].part = _ptr(part, C.c_int32)
+            items[i].eps_r = _ptr(eps, C.c_double)
+        opt = _options(**kw)
+        a = complex(alpha)
+        h = _h()
+        _check(_lib.d3m_setup_batch(items, len(problems), float(k), d3m_c128(a.real, a.imag), C.byref(opt),
+                                    C.byref(h)))
+        obj = cls.__new__(cls)
+        obj._adopt(h, k, opt)
+        return obj
+
+    def _adopt(self, h, k, opt):
         self._handle = h
         self.k = float(k)
-        self.host_only = bool(host_only)
+        self.host_only = bool(opt.host_only)
         self.info = self.query()
         self.n_edges = self.info["n_edges"]
         self.n_tets = self.info["n_tets"]
@@ -216,6 +277,26 @@ class Solver:
                                       C.c_void_p(f.ctypes.data)))
         return f
 
+    def rhs_planewave_batch(self, dirs, pols):
+        """dirs, pols [count][nrhs][3]: each problem of a batch with its own waves."""
+        d = np.ascontiguousarray(dirs, dtype=np.float64)
+        p = np.ascontiguousarray(pols, dtype=np.float64)
+        if d.ndim != 3 or d.shape != p.shape or d.shape[0] != self.layout()[0]:
+            raise ValueError("dirs and pols must be [count][nrhs][3]")
+        f = np.zeros((d.shape[1], self.n_edges), dtype=np.complex128)
+        _check(_lib.d3m_rhs_planewave_batch(self._handle, _ptr(d, C.c_double), _ptr(p, C.c_double), d.shape[1],
+                                            C.c_void_p(f.ctypes.data)))
+        return f
+
+    def layout(self):
+        """(count, edge_off[count + 1], tet_off[count + 1]) of a batch."""
+        n = C.c_int32()
+        _check(_lib.d3m_batch_layout(self._handle, C.byref(n), None, None))
+        eo = np.zeros(n.value + 1, dtype=np.int64)
+        to = np.zeros(n.value + 1, dtype=np.int64)
+        _check(_lib.d3m_batch_layout(self._handle, None, _ptr(eo, C.c_int64), _ptr(to, C.c_int64)))
+        return n.value, eo, to
+
     def probe(self, points):
         pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
         n = pts.shape[0]
@@ -229,6 +310,24 @@ class Solver:
         inf = d3m_info()
         _check(_lib.d3m_query(self._handle, C.byref(inf)))
         return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name != "reserved"}
+
+    TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks")
+
+    def tuning(self):
+        t = d3m_tuning()
+        _check(_lib.d3m_get_tuning(self._handle, C.byref(t)))
+        return {k: getattr(t, k) for k in self.TUNING_KEYS}
+
+    def set_tuning(self, **kw):
+        """Change launch-shape choices (keys of TUNING_KEYS; 0 = default).  A
+        new s1_block re-plans the factor schedule and drops the factors."""
+        t = d3m_tuning()
+        _check(_lib.d3m_get_tuning(self._handle, C.byref(t)))
+        for k, v in kw.items():
+            if k not in self.TUNING_KEYS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(_lib.d3m_set_tuning(self._handle, C.byref(t)))
 
     def set_profile(self, level):
         """Profiling level for later calls: 0 off, 1 update GEMMs only, 2 all."""

@@ -55,6 +55,13 @@ struct d3m_problem {
     d3m_options opt{};
     int factored = 0;  // 0 none, 1 fp64, 2 fp32
     bool device_ready = false;
+    // independent problems held by the handle (one for d3m_setup): edges and
+    // tetrahedra of problem p are [off[p], off[p + 1]) of the global numbering
+    int n_problems = 1;
+    std::vector<int64_t> prob_edge_off, prob_tet_off;
+    std::vector<int> sub_prob;      // problem of every subdomain
+    std::vector<int32_t> eprob;     // problem of every edge
+    int32_t *d_eprob = nullptr;
     // device: task lists and maps
     std::vector<DevBuf> bufs;
     BkTask *d_bk = nullptr;
@@ -104,8 +111,36 @@ struct d3m_problem {
     struct Rec { int kid; hipEvent_t a, b; double flops; };
     std::vector<Rec> recs;
     size_t ev_next = 0;
+    // HIP graphs (opt.use_graph): the factor launch sequence per precision
+    // and the solve passes per (precision, buffers, nrhs, accumulate), each
+    // captured once on gstream and replayed there, ordered after the work
+    // already queued on the caller's stream and before its later work
+    struct Graph { hipGraph_t g = nullptr; hipGraphExec_t x = nullptr; };
+    struct SolveGraph { int pr; const void *f; void *E; int nrhs; bool acc; Graph gr; };
+    Graph fgraph[2];
+    std::vector<SolveGraph> sgraphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t g_in = nullptr, g_out = nullptr;
+    bool capturing = false;
+    static void destroy_graph(Graph &g) {
+        if (g.x) (void)hipGraphExecDestroy(g.x);
+        if (g.g) (void)hipGraphDestroy(g.g);
+        g = Graph{};
+    }
+    void drop_solve_graphs() {
+        for (auto &sg : sgraphs) destroy_graph(sg.gr);
+        sgraphs.clear();
+    }
+    void drop_graphs() {
+        destroy_graph(fgraph[0]);
+        destroy_graph(fgraph[1]);
+        drop_solve_graphs();
+    }
+    // launch-shape choices (d3m_set_tuning)
+    d3m_tuning tune{};
 
     ~d3m_problem() {
+        drop_graphs();
         for (auto &b : bufs) if (b.p) (void)hipFree(b.p);
         for (int pr = 0; pr < 2; ++pr) {
             for (auto &b : arr[pr]) if (b.p) (void)hipFree(b.p);
@@ -116,6 +151,9 @@ struct d3m_problem {
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         for (auto e : sync_pool) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
+        if (gstream) (void)hipStreamDestroy(gstream);
+        if (g_in) (void)hipEventDestroy(g_in);
+        if (g_out) (void)hipEventDestroy(g_out);
     }
 
     template <typename P>
@@ -127,6 +165,18 @@ struct d3m_problem {
         if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
         dst = reinterpret_cast<P *>(b.p);
         return D3M_OK;
+    }
+    // replaces a buffer made by upload() (same owner list)
+    template <typename P>
+    int reupload(P *&dst, const void *src, size_t bytes) {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i].p == (void *)dst) {
+                (void)hipFree(bufs[i].p);
+                bufs.erase(bufs.begin() + (long)i);
+                break;
+            }
+        dst = nullptr;
+        return upload(dst, src, bytes);
     }
     template <typename P>
     int zeros(P *&dst, size_t bytes) {
@@ -148,7 +198,10 @@ struct d3m_problem {
 
     // ---- profiling helpers
     // opt.profile: 0 off, 1 the update GEMMs only, 2 every kernel group
-    bool prof_wanted(int kid) const { return opt.profile >= 2 || (opt.profile == 1 && kid == KID_UPDATE); }
+    bool prof_wanted(int kid) const {
+        if (capturing) return false;  // graphs carry no timing events
+        return opt.profile >= 2 || (opt.profile == 1 && kid == KID_UPDATE);
+    }
     void prof_begin(int kid, hipEvent_t &a, hipStream_t s) {
         a = nullptr;
         if (!prof_wanted(kid)) return;
@@ -216,6 +269,32 @@ void build_global_csr(const Mesh &m, const Decomp &dc, double k, const double *e
     }
 }
 
+// task lists and maps of the plan (again after a re-plan: replace = true)
+int upload_schedules(d3m_problem *h, bool replace) {
+    const Plan &pl = h->pl;
+    int rc;
+#define UPS(dst, vec)                                                                                          \
+    if ((rc = replace ? h->reupload(dst, vec.data(), vec.size() * sizeof(vec[0]))                              \
+                      : h->upload(dst, vec.data(), vec.size() * sizeof(vec[0]))) != D3M_OK)                   \
+    return rc
+    UPS(h->d_bk, pl.bk);
+    UPS(h->d_gemm, pl.gemm);
+    UPS(h->d_pairs, pl.pairs);
+    UPS(h->d_scale, pl.scale);
+    UPS(h->d_asm, pl.asmb);
+    UPS(h->d_vdiag, pl.vdiag);
+    UPS(h->d_vupd, pl.vupd);
+    UPS(h->d_vpairs, pl.vpairs);
+    UPS(h->d_vfuse, pl.vfuse);
+    UPS(h->d_coo_off, pl.coo_off);
+    UPS(h->d_split, pl.split_map);
+    UPS(h->d_collect, pl.collect_map);
+    UPS(h->d_hmap, pl.h_map);
+    UPS(h->d_lmap, pl.lam_map);
+#undef UPS
+    return D3M_OK;
+}
+
 int setup_device(d3m_problem *h) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(D3M_ENODEV, "no HIP device");
@@ -223,25 +302,16 @@ int setup_device(d3m_problem *h) {
     HIPCHK(hipSetDevice(h->opt.device));
     // default priority (the same as the caller's streams)
     HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->g_out, hipEventDisableTiming));
     h->sync_pool.resize(512);
     for (auto &e : h->sync_pool) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     Plan &pl = h->pl;
     int rc;
+    if ((rc = upload_schedules(h, false)) != D3M_OK) return rc;
 #define UP(dst, vec) if ((rc = h->upload(dst, vec.data(), vec.size() * sizeof(vec[0]))) != D3M_OK) return rc
-    UP(h->d_bk, pl.bk);
-    UP(h->d_gemm, pl.gemm);
-    UP(h->d_pairs, pl.pairs);
-    UP(h->d_scale, pl.scale);
-    UP(h->d_asm, pl.asmb);
-    UP(h->d_vdiag, pl.vdiag);
-    UP(h->d_vupd, pl.vupd);
-    UP(h->d_vpairs, pl.vpairs);
-    UP(h->d_vfuse, pl.vfuse);
-    UP(h->d_coo_off, pl.coo_off);
-    UP(h->d_split, pl.split_map);
-    UP(h->d_collect, pl.collect_map);
-    UP(h->d_hmap, pl.h_map);
-    UP(h->d_lmap, pl.lam_map);
+    UP(h->d_eprob, h->eprob);
     if ((rc = h->zeros(h->d_status, sizeof(int) * (pl.n_status + 1))) != D3M_OK) return rc;
     size_t dr = (size_t)std::max<i64>(pl.d_rows, 1);
     if ((rc = h->zeros(h->D.d, dr * sizeof(double2))) != D3M_OK) return rc;
@@ -313,6 +383,7 @@ template <typename T>
 int ensure_vectors(d3m_problem *h, int nrhs) {
     const int pr = std::is_same<T, double>::value ? 0 : 1;
     if (h->vec_nrhs[pr] >= nrhs) return D3M_OK;
+    h->drop_solve_graphs();  // they hold the old vector addresses
     const size_t es = sizeof(T) * 2;
     const Plan &pl = h->pl;
     for (int v = 0; v < VARR_COUNT; ++v) {
@@ -340,12 +411,13 @@ VBases vbases_of(d3m_problem *h) {
 // next-column updates of step j wait for the side-stream updates of step
 // j - 1 (which also reach those columns), and a side-stream launch starts
 // only after the panels it reads are scaled.
-constexpr i64 kLookaheadMinTasks = 512;
+constexpr i64 kLookaheadMinTasks = 512;  // default of d3m_tuning.lookahead_tasks
 
 template <typename T>
 int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
     hipStream_t s2 = h->side;
     hipEvent_t rest_done = nullptr;
+    const i64 min_split = h->tune.lookahead_tasks > 0 ? h->tune.lookahead_tasks : kLookaheadMinTasks;
     for (const auto &st : steps) {
         hipEvent_t ev{};
         if (st.nbk > 0) {
@@ -366,7 +438,7 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
         }
         // small updates stay on one stream: a cross-stream hand-off costs
         // more than the overlap gains when the side launch is short
-        const bool split = st.nup - st.ncrit >= kLookaheadMinTasks;
+        const bool split = st.nup - st.ncrit >= min_split;
         const i64 ncrit = split ? st.ncrit : st.nup;
         const double crit_flops = split ? st.crit_flops : st.up_flops;
         const i64 nrest = st.nup - ncrit;
@@ -396,23 +468,74 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
     return D3M_OK;
 }
 
+// Captures the launches body(gstream) makes into g (nothing runs).
+template <typename F>
+int capture_graph(d3m_problem *h, d3m_problem::Graph &g, F &&body) {
+    HIPCHK(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    h->capturing = true;
+    const int rc = body(h->gstream);
+    h->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->gstream, &graph);
+    if (rc != D3M_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(D3M_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(D3M_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    g.g = graph;
+    g.x = x;
+    return D3M_OK;
+}
+
+// Replays g on gstream after the work queued on s; later work on s waits for it.
+int replay_graph(d3m_problem *h, const d3m_problem::Graph &g, hipStream_t s) {
+    HIPCHK(hipEventRecord(h->g_in, s));
+    HIPCHK(hipStreamWaitEvent(h->gstream, h->g_in, 0));
+    HIPCHK(hipGraphLaunch(g.x, h->gstream));
+    HIPCHK(hipEventRecord(h->g_out, h->gstream));
+    HIPCHK(hipStreamWaitEvent(s, h->g_out, 0));
+    return D3M_OK;
+}
+
+// every launch of the factorisation (recipe steps 1, 2, 5), in order, on s
 template <typename T>
-int factor_impl(d3m_problem *h, hipStream_t s) {
-    int rc = ensure_arrays<T>(h);
-    if (rc != D3M_OK) return rc;
+int factor_launch(d3m_problem *h, hipStream_t s) {
     const Plan &pl = h->pl;
     Bases b = bases_of<T>(h);
+    int rc;
     hipEvent_t ev{};
     h->prof_begin(KID_ASM, ev, s);
     HIPCHK(launch_fill_zero<T>(b.p[ARR_M], pl.m_tiles * TILE_ELEMS, s));
     HIPCHK(launch_coo_scatter<T>(b.p[ARR_M], h->d_coo_off, h->d_coo_val, (int64_t)pl.coo_off.size(), s));
-    HIPCHK(hipMemsetAsync(h->d_status, 0, sizeof(int) * (pl.n_status + 1), s));
+    HIPCHK(launch_zero_i32(h->d_status, pl.n_status + 1, s));
     h->prof_end(KID_ASM, ev, 0.0, s);
     if ((rc = run_factor_sweep<T>(h, pl.s1_steps, b, s)) != D3M_OK) return rc;
     h->prof_begin(KID_ASM, ev, s);
     HIPCHK(launch_asm<T>(h->d_asm, (int64_t)pl.asmb.size(), b, s));
     h->prof_end(KID_ASM, ev, 0.0, s);
-    if ((rc = run_factor_sweep<T>(h, pl.k_steps, b, s)) != D3M_OK) return rc;
+    return run_factor_sweep<T>(h, pl.k_steps, b, s);
+}
+
+template <typename T>
+int factor_impl(d3m_problem *h, hipStream_t s) {
+    int rc = ensure_arrays<T>(h);
+    if (rc != D3M_OK) return rc;
+    const Plan &pl = h->pl;
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    if (h->opt.use_graph) {
+        if (!h->fgraph[pr].x &&
+            (rc = capture_graph(h, h->fgraph[pr], [&](hipStream_t gs) { return factor_launch<T>(h, gs); })) != D3M_OK)
+            return rc;
+        if ((rc = replay_graph(h, h->fgraph[pr], s)) != D3M_OK) return rc;
+    } else if ((rc = factor_launch<T>(h, s)) != D3M_OK) {
+        return rc;
+    }
     std::vector<int> status(pl.n_status + 1, 0);
     HIPCHK(hipMemcpyAsync(status.data(), h->d_status, sizeof(int) * status.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -441,19 +564,19 @@ int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases
                hipStream_t s) {
     if (st.up_first)
         HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
-                              vb, h->D, nrhs, s));
-    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, s));
+                              vb, h->D, nrhs, h->tune.solve_cols, s));
+    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, h->tune.solve_cols, s));
     if (!st.up_first)
         HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
-                              vb, h->D, nrhs, s));
+                              vb, h->D, nrhs, h->tune.solve_cols, s));
     return D3M_OK;
 }
 
-// E (=|+=) S^{-1} f through the factors of precision T; f and E on the device
+// E (=|+=) S^{-1} f through the factors of precision T; f and E on the
+// device; every launch of recipe steps 6-7, in order, on s
 template <typename T>
-int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
-    int rc = ensure_vectors<T>(h, nrhs);
-    if (rc != D3M_OK) return rc;
+int solve_launch(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
+    int rc;
     const Plan &pl = h->pl;
     Bases b = bases_of<T>(h);
     VBases vb = vbases_of<T>(h);
@@ -472,6 +595,32 @@ int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accu
     return D3M_OK;
 }
 
+template <typename T>
+int solve_pass(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
+    int rc = ensure_vectors<T>(h, nrhs);
+    if (rc != D3M_OK) return rc;
+    if (!h->opt.use_graph) return solve_launch<T>(h, f, E, nrhs, accumulate, s);
+    const int pr = std::is_same<T, double>::value ? 0 : 1;
+    d3m_problem::Graph *g = nullptr;
+    for (auto &sg : h->sgraphs)
+        if (sg.pr == pr && sg.f == f && sg.E == E && sg.nrhs == nrhs && sg.acc == accumulate) g = &sg.gr;
+    if (!g) {
+        constexpr size_t kMaxSolveGraphs = 8;
+        if (h->sgraphs.size() >= kMaxSolveGraphs) {
+            d3m_problem::destroy_graph(h->sgraphs.front().gr);
+            h->sgraphs.erase(h->sgraphs.begin());
+        }
+        h->sgraphs.push_back({pr, f, E, nrhs, accumulate, {}});
+        g = &h->sgraphs.back().gr;
+        rc = capture_graph(h, *g, [&](hipStream_t gs) { return solve_launch<T>(h, f, E, nrhs, accumulate, gs); });
+        if (rc != D3M_OK) {
+            h->sgraphs.pop_back();
+            return rc;
+        }
+    }
+    return replay_graph(h, *g, s);
+}
+
 bool is_device_ptr(const void *p) {
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
@@ -488,26 +637,37 @@ int fetch_norms(d3m_problem *h, int nrhs, std::vector<double> &out, hipStream_t 
     return D3M_OK;
 }
 
+// per problem and right-hand side: max_e |v[c][e]| over the problem's edges
 int norms_inf(d3m_problem *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t s) {
-    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
+    const size_t n = (size_t)h->n_problems * nrhs;
+    int rc = h->ensure(h->norms, sizeof(unsigned long long) * n);
     if (rc) return rc;
-    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
-    HIPCHK(launch_rownorm_max((unsigned long long *)h->norms.p, v, h->mesh.ne, nrhs, s));
-    return fetch_norms(h, nrhs, out, s);
+    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * n, s));
+    HIPCHK(launch_rownorm_max((unsigned long long *)h->norms.p, v, h->d_eprob, h->mesh.ne, nrhs, s));
+    return fetch_norms(h, (int)n, out, s);
 }
 
-// r = f - S E into h->stage_r (FP64) and the per-column infinity norms of r
+// r = f - S E into h->stage_r (FP64) and, per problem and right-hand side,
+// the infinity norm of r
 int residual_inf(d3m_problem *h, const double2 *f, const double2 *E, int nrhs, std::vector<double> &out,
                  hipStream_t s) {
-    int rc = h->ensure(h->norms, sizeof(unsigned long long) * nrhs);
+    const size_t n = (size_t)h->n_problems * nrhs;
+    int rc = h->ensure(h->norms, sizeof(unsigned long long) * n);
     if (rc) return rc;
-    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * nrhs, s));
+    HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * n, s));
     hipEvent_t ev{};
     h->prof_begin(KID_RESID, ev, s);
-    HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->mesh.ne, nrhs,
-                           (unsigned long long *)h->norms.p, s));
+    HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->d_eprob, h->mesh.ne,
+                           nrhs, (unsigned long long *)h->norms.p, s));
     h->prof_end(KID_RESID, ev, 0.0, s);
-    return fetch_norms(h, nrhs, out, s);
+    return fetch_norms(h, (int)n, out, s);
+}
+
+// max over problems and right-hand sides of ||r||_inf / ||f||_inf
+double relative_residual(const std::vector<double> &rn, const std::vector<double> &fn) {
+    double res = 0.0;
+    for (size_t i = 0; i < rn.size(); ++i) res = std::max(res, fn[i] > 0 ? rn[i] / fn[i] : rn[i]);
+    return res;
 }
 
 // full solve on device buffers (both precisions); optional diagnostics
@@ -521,8 +681,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
             std::vector<double> rn, fn;
             if ((rc = residual_inf(h, f, E, nrhs, rn, s))) return rc;
             if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
-            double res = 0.0;
-            for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
+            const double res = relative_residual(rn, fn);
             info->iterations = 0;
             info->converged = 1;
             info->residual = res;
@@ -542,8 +701,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     bool ok = false;
     for (;;) {
         if ((rc = residual_inf(h, f, E, nrhs, rn, s))) return rc;
-        res = 0.0;
-        for (int c = 0; c < nrhs; ++c) res = std::max(res, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
+        res = relative_residual(rn, fn);
         if (res <= h->opt.ir_tol) { ok = true; break; }
         if (it >= h->opt.ir_max_iter) break;
         if ((rc = solve_pass<float>(h, (double2 *)h->stage_r.p, E, nrhs, true, s))) return rc;
@@ -563,6 +721,73 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
 
 }  // namespace
 
+namespace {
+
+// Host setup of a handle (mesh, decomposition, ordering, plan), then the
+// device upload.  sub_group: problem of every subdomain (empty: one problem).
+int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz, int64_t nt, const int64_t *tets,
+                 const int32_t *part, const double *eps_r, double k, d3m_c128 alpha, const d3m_options *opt,
+                 std::vector<int> sub_group) {
+    if (opt) h->opt = *opt; else d3m_default_options(&h->opt);
+    if (h->opt.quad_points <= 0) h->opt.quad_points = 12;
+    if (h->opt.ir_max_iter <= 0 && !opt) h->opt.ir_max_iter = 10;
+    if (!(h->opt.ir_tol > 0)) h->opt.ir_tol = 1e-10;
+    try {
+        build_mesh(h->mesh, nv, xyz, nt, tets);
+        h->k = k;
+        h->alpha = cplx(alpha.re, alpha.im);
+        h->eps.assign(eps_r, eps_r + nt);
+        build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
+        if (!sub_group.empty() && (int)sub_group.size() != h->dc.N)
+            throw Error{-1, "a problem of the batch has an empty subdomain"};
+        order_blocks(h->bo, h->dc, h->mesh, sub_group);
+        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block);
+    } catch (const Error &e) {
+        return fail(D3M_EINVAL, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(D3M_ENOMEM, "host allocation failed in setup");
+    }
+    h->tune.s1_block = h->opt.s1_block;
+    h->sub_prob = sub_group.empty() ? std::vector<int>(h->dc.N, 0) : sub_group;
+    if (h->prob_edge_off.empty()) h->prob_edge_off = {0, h->mesh.ne};
+    if (h->prob_tet_off.empty()) h->prob_tet_off = {0, h->mesh.nt};
+    h->eprob.assign(h->mesh.ne, 0);
+    for (int p = 0; p < h->n_problems; ++p)
+        for (int64_t e = h->prob_edge_off[p]; e < h->prob_edge_off[p + 1]; ++e) h->eprob[e] = p;
+    if (!h->opt.host_only) {
+        int rc = setup_device(h.get());
+        if (rc != D3M_OK) return rc;
+    }
+    return D3M_OK;
+}
+
+}  // namespace
+
+namespace {
+// plane-wave loads of every boundary face; the face's problem p takes the
+// direction and polarisation at dirs + 3 * (p * pstride + c)
+void planewave_loads(d3m_problem *h, const double *dirs, const double *pols, int32_t nrhs, int32_t pstride,
+                     d3m_c128 *f) {
+    std::vector<double> qs, qt, qw;
+    triangle_rule(h->opt.quad_points, qs, qt, qw);
+    const int64_t ne = h->mesh.ne;
+    std::memset(f, 0, sizeof(d3m_c128) * (size_t)nrhs * ne);
+    for (int c = 0; c < nrhs; ++c) {
+        for (i64 fi : h->dc.bface) {
+            const int p = h->eprob[h->mesh.face_edges[3 * fi]];
+            const size_t o = 3 * ((size_t)p * pstride + c);
+            cplx out[3];
+            face_planewave_load(h->mesh, fi, h->k, dirs + o, pols + o, qs, qt, qw, out);
+            for (int a = 0; a < 3; ++a) {
+                d3m_c128 &x = f[(size_t)c * ne + h->mesh.face_edges[3 * fi + a]];
+                x.re += out[a].real();
+                x.im += out[a].imag();
+            }
+        }
+    }
+}
+}  // namespace
+
 // =========================================================== C ABI ======
 extern "C" {
 
@@ -575,6 +800,43 @@ int d3m_set_profile(d3m_handle h, int level) {
     return D3M_OK;
 }
 
+int d3m_get_tuning(d3m_handle h, d3m_tuning *t) {
+    if (!h || !t) return fail(D3M_EINVAL, "null argument");
+    *t = h->tune;
+    return D3M_OK;
+}
+
+int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
+    if (!h || !t) return fail(D3M_EINVAL, "null argument");
+    if (t->s1_block < 0 || t->s1_block > 16) return fail(D3M_EINVAL, "s1_block must be in [0, 16]");
+    if (t->solve_cols != 0 && t->solve_cols != 16 && t->solve_cols != 32)
+        return fail(D3M_EINVAL, "solve_cols must be 0, 16 or 32");
+    if (t->lookahead_tasks < 0) return fail(D3M_EINVAL, "lookahead_tasks must be >= 0");
+    const int old_s1 = h->tune.s1_block;
+    h->drop_graphs();
+    h->tune = *t;
+    if (t->s1_block != old_s1) {
+        // the tile layout does not depend on the blocking: only the schedules change
+        Plan np;
+        try {
+            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block);
+        } catch (const Error &e) {
+            return fail(D3M_EINVAL, e.msg);
+        } catch (const std::bad_alloc &) {
+            return fail(D3M_ENOMEM, "host allocation failed in re-planning");
+        }
+        const Plan &op = h->pl;
+        if (np.m_tiles != op.m_tiles || np.k_tiles != op.k_tiles || np.tt_tiles != op.tt_tiles ||
+            np.d_rows != op.d_rows || np.n_status != op.n_status || np.bk_scratch_elems != op.bk_scratch_elems)
+            return fail(D3M_EINVAL, "internal: re-planning changed the storage layout");
+        h->pl = std::move(np);
+        h->opt.s1_block = t->s1_block;
+        h->factored = 0;
+        if (h->device_ready) return upload_schedules(h, true);
+    }
+    return D3M_OK;
+}
+
 void d3m_default_options(d3m_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -583,34 +845,98 @@ void d3m_default_options(d3m_options *o) {
     o->ir_tol = 1e-10;
 }
 
+
 int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r, double k, d3m_c128 alpha,
               const d3m_options *opt, d3m_handle *out) {
     if (!out) return fail(D3M_EINVAL, "null output handle");
     *out = nullptr;
     if (!mesh || !mesh->xyz || !mesh->tets || !part || !eps_r) return fail(D3M_EINVAL, "null argument");
     std::unique_ptr<d3m_problem> h(new d3m_problem());
-    if (opt) h->opt = *opt; else d3m_default_options(&h->opt);
-    if (h->opt.quad_points <= 0) h->opt.quad_points = 12;
-    if (h->opt.ir_max_iter <= 0 && !opt) h->opt.ir_max_iter = 10;
-    if (!(h->opt.ir_tol > 0)) h->opt.ir_tol = 1e-10;
-    try {
-        build_mesh(h->mesh, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets);
-        h->k = k;
-        h->alpha = cplx(alpha.re, alpha.im);
-        h->eps.assign(eps_r, eps_r + mesh->n_tets);
-        build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
-        order_blocks(h->bo, h->dc, h->mesh);
-        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block);
-    } catch (const Error &e) {
-        return fail(D3M_EINVAL, e.msg);
-    } catch (const std::bad_alloc &) {
-        return fail(D3M_ENOMEM, "host allocation failed in setup");
-    }
-    if (!h->opt.host_only) {
-        int rc = setup_device(h.get());
-        if (rc != D3M_OK) return rc;
-    }
+    int rc = setup_common(h, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, part, eps_r, k, alpha, opt, {});
+    if (rc != D3M_OK) return rc;
     *out = h.release();
+    return D3M_OK;
+}
+
+int d3m_setup_batch(const d3m_batch_item *items, int32_t count, double k, d3m_c128 alpha, const d3m_options *opt,
+                    d3m_handle *out) {
+    if (!out) return fail(D3M_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!items || count < 1) return fail(D3M_EINVAL, "a batch needs at least one problem");
+    std::unique_ptr<d3m_problem> h(new d3m_problem());
+    // disjoint union: vertex, tetrahedron and subdomain ids of problem p are
+    // shifted past those of problems 0 .. p-1
+    int64_t nv = 0, nt = 0;
+    for (int p = 0; p < count; ++p) {
+        const d3m_batch_item &it = items[p];
+        if (!it.mesh.xyz || !it.mesh.tets || !it.part || !it.eps_r) return fail(D3M_EINVAL, "null argument in batch");
+        if (it.mesh.n_vertices <= 0 || it.mesh.n_tets <= 0) return fail(D3M_EINVAL, "empty mesh in batch");
+        nv += it.mesh.n_vertices;
+        nt += it.mesh.n_tets;
+    }
+    std::vector<double> xyz;
+    std::vector<int64_t> tets;
+    std::vector<int32_t> part;
+    std::vector<double> eps;
+    std::vector<int> sub_group;
+    std::vector<int64_t> vert_off{0};
+    try {
+        xyz.reserve(3 * nv); tets.reserve(4 * nt); part.reserve(nt); eps.reserve(nt);
+        h->prob_tet_off.assign(1, 0);
+        int32_t sub0 = 0;
+        for (int p = 0; p < count; ++p) {
+            const d3m_batch_item &it = items[p];
+            const int64_t v0 = vert_off.back();
+            xyz.insert(xyz.end(), it.mesh.xyz, it.mesh.xyz + 3 * it.mesh.n_vertices);
+            for (int64_t x = 0; x < 4 * it.mesh.n_tets; ++x) {
+                const int64_t v = it.mesh.tets[x];
+                if (v < 0 || v >= it.mesh.n_vertices) return fail(D3M_EINVAL, "tetrahedron vertex id out of range");
+                tets.push_back(v + v0);
+            }
+            int32_t np = 0;
+            for (int64_t t = 0; t < it.mesh.n_tets; ++t) {
+                if (it.part[t] < 0) return fail(D3M_EINVAL, "negative subdomain id");
+                np = std::max(np, it.part[t] + 1);
+                part.push_back(it.part[t] + sub0);
+            }
+            eps.insert(eps.end(), it.eps_r, it.eps_r + it.mesh.n_tets);
+            for (int32_t d = 0; d < np; ++d) sub_group.push_back(p);
+            sub0 += np;
+            vert_off.push_back(v0 + it.mesh.n_vertices);
+            h->prob_tet_off.push_back(h->prob_tet_off.back() + it.mesh.n_tets);
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(D3M_ENOMEM, "host allocation failed in batch setup");
+    }
+    h->n_problems = count;
+    // edges are numbered by (lower vertex, higher vertex), so the edges of a
+    // problem form one contiguous range, in problem order
+    {
+        Mesh probe;
+        try {
+            build_mesh(probe, nv, xyz.data(), nt, tets.data());
+        } catch (const Error &e) {
+            return fail(D3M_EINVAL, e.msg);
+        }
+        h->prob_edge_off.assign(count + 1, probe.ne);
+        int p = 0;
+        h->prob_edge_off[0] = 0;
+        for (int64_t e = 0; e < probe.ne; ++e) {
+            while (probe.edges[2 * e] >= vert_off[p + 1]) h->prob_edge_off[++p] = e;
+        }
+        for (int q = p + 1; q <= count; ++q) h->prob_edge_off[q] = probe.ne;
+    }
+    int rc = setup_common(h, nv, xyz.data(), nt, tets.data(), part.data(), eps.data(), k, alpha, opt, sub_group);
+    if (rc != D3M_OK) return rc;
+    *out = h.release();
+    return D3M_OK;
+}
+
+int d3m_batch_layout(d3m_handle h, int32_t *count, int64_t *edge_off, int64_t *tet_off) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (count) *count = h->n_problems;
+    if (edge_off) std::copy(h->prob_edge_off.begin(), h->prob_edge_off.end(), edge_off);
+    if (tet_off) std::copy(h->prob_tet_off.begin(), h->prob_tet_off.end(), tet_off);
     return D3M_OK;
 }
 
@@ -717,29 +1043,24 @@ int d3m_adjoint(d3m_handle h, const d3m_c128 *grad_E, const d3m_c128 *E, int32_t
     return D3M_OK;
 }
 
+
 int d3m_rhs_planewave(d3m_handle h, const double *dirs, const double *pols, int32_t nrhs, d3m_c128 *f) {
     if (!h || !dirs || !pols || !f) return fail(D3M_EINVAL, "null argument");
     if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
-    std::vector<double> qs, qt, qw;
-    triangle_rule(h->opt.quad_points, qs, qt, qw);
-    const int64_t ne = h->mesh.ne;
-    std::memset(f, 0, sizeof(d3m_c128) * (size_t)nrhs * ne);
-    for (int c = 0; c < nrhs; ++c) {
-        for (i64 fi : h->dc.bface) {
-            cplx out[3];
-            face_planewave_load(h->mesh, fi, h->k, dirs + 3 * c, pols + 3 * c, qs, qt, qw, out);
-            for (int a = 0; a < 3; ++a) {
-                d3m_c128 &x = f[(size_t)c * ne + h->mesh.face_edges[3 * fi + a]];
-                x.re += out[a].real();
-                x.im += out[a].imag();
-            }
-        }
-    }
+    planewave_loads(h, dirs, pols, nrhs, 0, f);
+    return D3M_OK;
+}
+
+int d3m_rhs_planewave_batch(d3m_handle h, const double *dirs, const double *pols, int32_t nrhs, d3m_c128 *f) {
+    if (!h || !dirs || !pols || !f) return fail(D3M_EINVAL, "null argument");
+    if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
+    planewave_loads(h, dirs, pols, nrhs, nrhs, f);
     return D3M_OK;
 }
 
 int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges, double *coef) {
     if (!h || !pts || !edges || !coef) return fail(D3M_EINVAL, "null argument");
+    if (h->n_problems != 1) return fail(D3M_EINVAL, "probe needs a single-problem handle");
     const Mesh &m = h->mesh;
     static const int te[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
     for (int p = 0; p < n; ++p) {
@@ -795,6 +1116,8 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->factored = h->factored;
     info->n_units = h->pl.k_units;
     info->n_unit_levels = h->pl.k_levels;
+    info->n_problems = h->n_problems;
+    info->array_bytes = (2 * h->pl.m_tiles + 3 * h->pl.k_tiles + h->pl.tt_tiles) * (int64_t)TILE_ELEMS * 16;
     return D3M_OK;
 }
 
@@ -851,13 +1174,13 @@ int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf, int64
         const Subdomain &S = dc.sub[index];
         const Plan &pl = h->pl;
         const i64 m = S.m;
-        std::vector<double2> tiles((size_t)tri_slot(pl.T[index], 0) * TILE_ELEMS);
-        if (hipMemcpy(tiles.data(), (double2 *)h->arr[0][ARR_M].p + pl.m_base[index] * TILE_ELEMS,
+        std::vector<double2> tiles((size_t)tri_slot(pl.TL[index], 0) * TILE_ELEMS);
+        if (hipMemcpy(tiles.data(), (double2 *)h->arr[0][ARR_M].p + pl.m_tbase[index] * TILE_ELEMS,
                       tiles.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(D3M_EHIP, "copy of the subdomain tiles failed");
         for (i64 r = 0; r < m; ++r)
             for (i64 c = 0; c < m; ++c) {
-                i64 R = (i64)pl.TE[index] * TILE + std::max(r, c), C = (i64)pl.TE[index] * TILE + std::min(r, c);
+                i64 R = std::max(r, c), C = std::min(r, c);  // inside the trailing triangle
                 double2 v = tiles[tri_slot(R / TILE, C / TILE) * TILE_ELEMS + (C % TILE) * TILE + R % TILE];
                 double2 kd = make_double2(-v.x, -v.y);  // trailing block = -K_D
                 put(&kd, sizeof(kd));

@@ -244,8 +244,11 @@ void reassemble_values(Decomp &dc, const Mesh &m, double k, const double *eps) {
 // ------------------------------------------------------------------------
 // Steps 3-4: geometric nested dissection of the clique graph of K (blocks
 // adjacent when they share a subdomain) on subdomain centroids, then block
-// symbolic elimination and elimination-tree levels.
-void order_blocks(BlockOrder &bo, const Decomp &dc, const Mesh &m) {
+// symbolic elimination and elimination-tree levels.  sub_group (empty or one
+// entry per subdomain) splits the subdomains into independent problems whose
+// blocks never meet: each group is dissected on its own, one after another,
+// so the elimination tree is a forest with one tree per problem.
+void order_blocks(BlockOrder &bo, const Decomp &dc, const Mesh &m, const std::vector<int> &sub_group) {
     int N = dc.N, nb = dc.nblk;
     std::vector<double> cen(3 * N, 0.0);
     std::vector<i64> cnt(N, 0);
@@ -306,9 +309,17 @@ void order_blocks(BlockOrder &bo, const Decomp &dc, const Mesh &m) {
         sep.erase(std::unique(sep.begin(), sep.end()), sep.end());
         for (int b : sep) bo.order.push_back(b);
     };
-    std::vector<int> all(N);
-    std::iota(all.begin(), all.end(), 0);
-    rec(all);
+    if (sub_group.empty()) {
+        std::vector<int> all(N);
+        std::iota(all.begin(), all.end(), 0);
+        rec(all);
+    } else {
+        if ((int)sub_group.size() != N) throw Error{-1, "internal: subdomain groups do not match the partition"};
+        const int ng = *std::max_element(sub_group.begin(), sub_group.end()) + 1;
+        std::vector<std::vector<int>> groups(ng);
+        for (int d = 0; d < N; ++d) groups[sub_group[d]].push_back(d);
+        for (auto &g : groups) rec(g);
+    }
     if ((int)bo.order.size() != nb) throw Error{-1, "ordering did not cover every block"};
     bo.pos.assign(nb, -1);
     for (int j = 0; j < nb; ++j) bo.pos[bo.order[j]] = j;

@@ -28,7 +28,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     pl = Plan();
 
     // ------------------------------------------------------------ layouts --
-    pl.TE.resize(N); pl.TL.resize(N); pl.T.resize(N); pl.fb.resize(N); pl.m_base.resize(N);
+    pl.TE.resize(N); pl.TL.resize(N); pl.T.resize(N); pl.fb.resize(N);
     pl.tt_s1.resize(N); pl.drow_s1.resize(N);
     i64 slot = 0, tt = 0, drow = 0;
     int maxTE = 0;
@@ -38,15 +38,12 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         pl.TL[d] = ceil_div(S.m, TILE);
         pl.T[d] = pl.TE[d] + pl.TL[d];
         pl.fb[d] = (int)(S.nI / TILE);
-        pl.m_base[d] = slot;
-        slot += tri_slot(pl.T[d], 0);
         pl.tt_s1[d] = tt;
         tt += pl.TE[d];
         pl.drow_s1[d] = drow;
         drow += (i64)pl.TE[d] * TILE;
         maxTE = std::max(maxTE, pl.TE[d]);
     }
-    pl.m_tiles = slot;
 
     // Units of the LM Schur complement: the blocks in elimination order, each
     // split into ceil(n / unit_max) nearly equal consecutive pieces when
@@ -114,7 +111,6 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     pl.tt_tiles = tt;
     pl.d_rows = drow;
 
-    auto mslot = [&](int d, int a, int b) { return pl.m_base[d] + tri_slot(a, b); };
     auto mrows = [&](int d, int a) {
         const Subdomain &S = dc.sub[d];
         return a < pl.TE[d] ? tile_rows(S.n, a) : tile_rows(S.m, a - pl.TE[d]);
@@ -165,6 +161,32 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     for (int d = 0; d < N; ++d)
         for (int a = 0; a < pl.T[d]; ++a)
             for (int b = 0; b <= a && b < pl.TE[d]; ++b) pl.s1_tiles += nz[d][a][b];
+
+    // ARR_M holds, per subdomain, only the structurally nonzero tiles of the
+    // eliminated tile columns (column by column), then the whole trailing
+    // multiplier triangle (tile (TE, TE) onwards, packed lower triangle),
+    // which the assembly of -K reads at arbitrary row offsets.
+    pl.m_cslot.assign(N, {});
+    pl.m_tbase.assign(N, 0);
+    slot = 0;
+    for (int d = 0; d < N; ++d) {
+        const int T = pl.T[d], TEd = pl.TE[d];
+        auto &cs = pl.m_cslot[d];
+        cs.assign((size_t)T * TEd, -1);
+        for (int b = 0; b < TEd; ++b)
+            for (int a = b; a < T; ++a)
+                if (nz[d][a][b]) cs[(size_t)a * TEd + b] = slot++;
+        pl.m_tbase[d] = slot;
+        slot += tri_slot(pl.TL[d], 0);
+    }
+    pl.m_tiles = slot;
+    auto mslot = [&](int d, int a, int b) -> i64 {
+        const int TEd = pl.TE[d];
+        if (b >= TEd) return pl.m_tbase[d] + tri_slot(a - TEd, b - TEd);
+        const i64 x = pl.m_cslot[d][(size_t)a * TEd + b];
+        if (x < 0) throw Error{-1, "internal: a zero tile of a subdomain matrix is addressed"};
+        return x;
+    };
 
     // --------------------------------------------- step 1 (subdomain) plan --
     for (int j = 0; j < maxTE; ++j) {
@@ -246,6 +268,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                     for (int b = jend; b < pl.T[d]; ++b) {
                         if ((b < jend + S1_BLOCK) != (pass == 0)) continue;
                         for (int a = b; a < pl.T[d]; ++a) {
+                            if (b < pl.TE[d] && !nz[d][a][b]) continue;  // no pair reaches a zero tile
                             GemmTask g{E(ARR_M, mslot(d, a, b)), (int32_t)pl.pairs.size(), 0};
                             const int ra = mrows(d, a), rb = mrows(d, b);
                             for (int jj = j0; jj < jlast; ++jj) {
@@ -295,9 +318,9 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                         const Subdomain &S = dc.sub[d];
                         auto oP = std::lower_bound(S.blocks.begin(), S.blocks.end(), P) - S.blocks.begin();
                         auto oQ = std::lower_bound(S.blocks.begin(), S.blocks.end(), Q) - S.blocks.begin();
-                        t.mbase[c] = pl.m_base[d];
-                        t.row0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oP] + uoff[i] + (i64)a * TILE);
-                        t.col0[c] = (int32_t)((i64)pl.TE[d] * TILE + S.block_off[oQ] + uoff[j] + (i64)b * TILE);
+                        t.mbase[c] = pl.m_tbase[d];
+                        t.row0[c] = (int32_t)(S.block_off[oP] + uoff[i] + (i64)a * TILE);
+                        t.col0[c] = (int32_t)(S.block_off[oQ] + uoff[j] + (i64)b * TILE);
                     }
                     pl.asmb.push_back(t);
                 }

@@ -37,7 +37,8 @@ struct SolveStep {
 struct Plan {
     // ---- subdomain matrices M_d = [A_d D_d; D_d^T 0] --------------------
     std::vector<int> TE, TL, T, fb;    // E tiles, LM tiles, total, first tile column holding interface rows
-    std::vector<i64> m_base;           // tile slot of tile (0,0) of each subdomain in ARR_M
+    std::vector<std::vector<i64>> m_cslot;  // per subdomain: slot of tile (a, b < TE) at a * TE + b, -1 if zero
+    std::vector<i64> m_tbase;          // slot of the trailing tile (TE, TE); the trailing triangle is packed
     i64 m_tiles = 0;
     i64 s1_tiles = 0;                  // structurally nonzero tiles in the eliminated columns
     // ---- LM Schur complement (-K), elimination-position order -----------

@@ -109,6 +109,6 @@ struct BlockOrder {
     int n_levels = 0;
 };
 
-void order_blocks(BlockOrder &bo, const Decomp &dc, const Mesh &m);
+void order_blocks(BlockOrder &bo, const Decomp &dc, const Mesh &m, const std::vector<int> &sub_group);
 
 }  // namespace d3m

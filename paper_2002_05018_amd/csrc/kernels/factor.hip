@@ -757,6 +757,17 @@ hipError_t launch_fill_zero(void *p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void zero_i32_kernel(int *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+// (a kernel, not a memset, so that it can sit in a captured graph)
+hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_coo_scatter(void *M, const int64_t *off, const double2 *val, int64_t n, hipStream_t s) {
     using T2 = typename C2T<T>::type;

@@ -21,6 +21,7 @@ struct VBases {
 };
 
 template <typename T> hipError_t launch_fill_zero(void *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_coo_scatter(void *M, const int64_t *off, const double2 *val, int64_t n, hipStream_t s);
 template <typename T>
@@ -41,13 +42,14 @@ template <typename T> hipError_t launch_asm(const AsmTask *tasks, int64_t ntask,
 template <typename T>
 hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t nrows, int nrhs, int64_t ne,
                          hipStream_t s);
+// cols: right-hand sides per work-group (16 or 32; 0 = 32)
 template <typename T>
 hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
-                        const DArrays &D, int nrhs, hipStream_t s);
+                        const DArrays &D, int nrhs, int cols, hipStream_t s);
 template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                        const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
-                       hipStream_t s);
+                       int cols, hipStream_t s);
 template <typename T>
 hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s);
 template <typename T>
@@ -58,10 +60,14 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
                            hipStream_t s);
 
 // refinement and adjoint
-// r = f - S E, with max_e |r[c][e]| folded into nmax[c] (zeroed by the caller)
+// r = f - S E; the largest |r| over the rows of each problem (eprob: problem
+// of every row) and right-hand side is folded into nmax[p * nrhs + c]
+// (zeroed by the caller)
 hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, int64_t ne, int nrhs, unsigned long long *nmax, hipStream_t s);
-hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s);
+                           const double2 *val, const int32_t *eprob, int64_t ne, int nrhs, unsigned long long *nmax,
+                           hipStream_t s);
+hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne, int nrhs,
+                              hipStream_t s);
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s);
 hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E, const int64_t *tet_edges,
                                const double *mass, double k2, int64_t nt, int64_t ne, int nrhs, hipStream_t s);

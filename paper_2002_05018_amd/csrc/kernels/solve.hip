@@ -388,17 +388,30 @@ __global__ void vcollect_kernel(double2 *E, const T2 *X, const int64_t *cmap, in
     E[idx] = ACC ? cadd(E[idx], v) : v;
 }
 
+// Folds v >= 0 of a lane into nmax[g] (per-lane group g, nmax holds bit
+// patterns of non-negative doubles, monotone under unsigned comparison).  A
+// wave whose lanes share one group reduces first and issues one atomic.
+__device__ __forceinline__ void fold_max(unsigned long long *nmax, int64_t g, double v, bool live) {
+    const int64_t g0 = __shfl(g, 0), g63 = __shfl(g, 63);
+    if (g0 == g63) {
+        for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if ((threadIdx.x & 63) == 0 && g0 >= 0) atomicMax(&nmax[g0], (unsigned long long)__double_as_longlong(v));
+    } else if (live && g >= 0) {
+        atomicMax(&nmax[g], (unsigned long long)__double_as_longlong(v));
+    }
+}
+
 // r = f - S E (CSR of the global FEM matrix, FP64).  One thread per row and
 // RES_COLS right-hand sides (blockIdx.y selects them): the row's entries are
 // read once for all of them, and the gathers of E for one entry are
-// independent of each other.  nmax[c] (zeroed by the caller) gets
-// max_e |r[c][e]| (modulus) as the bit pattern of a non-negative double
-// (monotone under unsigned comparison).
+// independent of each other.  nmax[p * nrhs + c] (zeroed by the caller) gets
+// the largest |r[c][e]| (modulus) over the rows e of problem p = eprob[e].
 constexpr int RES_COLS = 16;
 
 __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *E,
                                                        const int64_t *rowptr, const int32_t *col, const double2 *val,
-                                                       int64_t ne, int nrhs, unsigned long long *nmax) {
+                                                       const int32_t *eprob, int64_t ne, int nrhs,
+                                                       unsigned long long *nmax) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c0 = blockIdx.y * RES_COLS;
     const int nc = min(RES_COLS, nrhs - c0);
@@ -406,7 +419,9 @@ __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2
     double2 s[RES_COLS];
 #pragma unroll
     for (int c = 0; c < RES_COLS; ++c) s[c] = make_double2(0, 0);
+    int64_t pbase = -1;
     if (live) {
+        pbase = (int64_t)eprob[row] * nrhs + c0;
 #pragma unroll
         for (int c = 0; c < RES_COLS; ++c)
             if (c < nc) s[c] = f[(int64_t)(c0 + c) * ne + row];
@@ -423,24 +438,25 @@ __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2
             if (c < nc) r[(int64_t)(c0 + c) * ne + row] = s[c];
     }
 #pragma unroll
-    for (int c = 0; c < RES_COLS; ++c) {
-        double m = sqrt(s[c].x * s[c].x + s[c].y * s[c].y);
-        for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if ((threadIdx.x & 63) == 0 && c < nc) atomicMax(&nmax[c0 + c], (unsigned long long)__double_as_longlong(m));
-    }
+    for (int c = 0; c < RES_COLS; ++c)
+        if (c < nc) fold_max(nmax, live ? pbase + c : -1, sqrt(s[c].x * s[c].x + s[c].y * s[c].y), live);
 }
 
-// out[c] = max_e |v[c][e]| (infinity norm with |z| = modulus), as the bit
-// pattern of a non-negative double (monotone under unsigned comparison)
-__global__ void rownorm_max_kernel(unsigned long long *out, const double2 *v, int64_t ne, int nrhs) {
-    int c = blockIdx.y;
+// nmax[p * nrhs + c] = max |v[c][e]| over the rows e of problem p (|z| =
+// modulus); one thread per element, blockIdx.y = right-hand side
+__global__ void rownorm_max_kernel(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne,
+                                   int nrhs) {
+    const int c = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = e < ne;
     double m = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
-        double2 z = v[(int64_t)c * ne + e];
-        m = fmax(m, sqrt(z.x * z.x + z.y * z.y));
+    int64_t g = -1;
+    if (live) {
+        const double2 z = v[(int64_t)c * ne + e];
+        m = sqrt(z.x * z.x + z.y * z.y);
+        g = (int64_t)eprob[e] * nrhs + c;
     }
-    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&out[c], (unsigned long long)__double_as_longlong(m));
+    fold_max(nmax, g, m, live);
 }
 
 __global__ void conj_kernel(double2 *out, const double2 *in, int64_t n) {
@@ -481,17 +497,18 @@ hipError_t launch_vsplit(void *X, const double2 *f, const int64_t *map, int64_t 
     hipLaunchKernelGGL(vsplit_kernel<T2>, g1(nrows * nrhs), dim3(256), 0, s, (T2 *)X, f, map, nrows, nrhs, ne);
     return hipGetLastError();
 }
-// right-hand sides per work-group: 16 (one MFMA column block) or 32
-inline int sv_ncb(int nrhs) { return nrhs <= 16 ? 1 : 2; }
+// right-hand sides per work-group: 16 (one MFMA column block) or 32; cols
+// (16 or 32, 0 = 32) caps it
+inline int sv_ncb(int nrhs, int cols) { return nrhs <= 16 || cols == 16 ? 1 : 2; }
 inline unsigned sv_groups(int64_t ntask) { return (unsigned)(((ntask + kXcds - 1) / kXcds) * kXcds); }
 
 template <typename T>
 hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bwd, const Bases &b, const VBases &vb,
-                        const DArrays &D, int nrhs, hipStream_t s) {
+                        const DArrays &D, int nrhs, int cols, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
     if (maxt <= 1) {
-        const int ncb = sv_ncb(nrhs);
+        const int ncb = sv_ncb(nrhs, cols);
         dim3 grid(sv_groups(ntask), (unsigned)((nrhs + 16 * ncb - 1) / (16 * ncb)));
         if (ncb == 1) {
             if (bwd) hipLaunchKernelGGL((vdiag_kernel<T, true, 1>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
@@ -526,9 +543,9 @@ void launch_vupd_ncb(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, 
 template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                        const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
-                       hipStream_t s) {
+                       int cols, hipStream_t s) {
     if (ntask <= 0) return hipSuccess;
-    if (sv_ncb(nrhs) == 1) launch_vupd_ncb<T, 1>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
+    if (sv_ncb(nrhs, cols) == 1) launch_vupd_ncb<T, 1>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
     else launch_vupd_ncb<T, 2>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
     return hipGetLastError();
 }
@@ -560,16 +577,15 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
 }
 
 hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, int64_t ne, int nrhs, unsigned long long *nmax, hipStream_t s) {
+                           const double2 *val, const int32_t *eprob, int64_t ne, int nrhs, unsigned long long *nmax,
+                           hipStream_t s) {
     dim3 grid(g1(ne).x, (unsigned)((nrhs + RES_COLS - 1) / RES_COLS));
-    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, r, f, E, rowptr, col, val, ne, nrhs, nmax);
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, r, f, E, rowptr, col, val, eprob, ne, nrhs, nmax);
     return hipGetLastError();
 }
-hipError_t launch_rownorm_max(unsigned long long *out, const double2 *v, int64_t ne, int nrhs, hipStream_t s) {
-    int64_t blocks = (ne + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(rownorm_max_kernel, dim3((unsigned)blocks, (unsigned)nrhs), dim3(256), 0, s, out, v, ne, nrhs);
+hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne, int nrhs,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(rownorm_max_kernel, dim3(g1(ne).x, (unsigned)nrhs), dim3(256), 0, s, nmax, v, eprob, ne, nrhs);
     return hipGetLastError();
 }
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s) {
@@ -586,10 +602,10 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
     template hipError_t launch_vsplit<T>(void *, const double2 *, const int64_t *, int64_t, int, int64_t,          \
                                          hipStream_t);                                                            \
     template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, int, bool, const Bases &, const VBases &,           \
-                                        const DArrays &, int, hipStream_t);                                       \
+                                        const DArrays &, int, int, hipStream_t);                                  \
     template hipError_t launch_vupd<T>(const VUpdTask *, const int64_t *, int64_t, const VUpdPair *,            \
                                        const VDiagTask *, int, const Bases &, const VBases &, const DArrays &, int, \
-                                       hipStream_t);                                         \
+                                       int, hipStream_t);                                                         \
     template hipError_t launch_vgather_h<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);     \
     template hipError_t launch_vscatter_lam<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);  \
     template hipError_t launch_vcollect<T>(double2 *, const void *, const int64_t *, int64_t, int, bool,           \

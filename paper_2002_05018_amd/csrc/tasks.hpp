@@ -63,8 +63,8 @@ struct ScaleTask {
 struct AsmTask {
     int64_t dst;
     int32_t nrow, ncol, ncontrib, pad;
-    int64_t mbase[2];  // element offset (ARR_M) of tile slot 0 of the subdomain
-    int32_t row0[2], col0[2];
+    int64_t mbase[2];  // tile slot (ARR_M) of the subdomain's trailing multiplier triangle
+    int32_t row0[2], col0[2];  // first row / column inside that triangle
 };
 
 // element offset of tile (a, b), a >= b, inside a packed lower tile triangle

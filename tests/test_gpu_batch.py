@@ -1,0 +1,139 @@
+"""GPU tests of the batching form, captured HIP graphs and the tuning knobs.
+
+* A batch of independent problems with uneven subdomains is factored and
+  solved as one handle; every problem's slice of the field must match the
+  CPU oracle run on that problem alone (1e-10, the method's exactness bar),
+  in FP64 and with FP32 factors plus FP64 refinement (residual 1e-10 per
+  problem and right-hand side, 1e-9 against the oracle).
+* Graph replays (opt.use_graph) must reproduce the eager launches bit for
+  bit, replay after replay, with eager work and synchronisations between the
+  replays and new right-hand-side values in the same buffer.
+* Other launch shapes (blocked-update depth, solve column block, look-ahead
+  threshold) change only the summation order: results agree to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_cache = {}
+
+
+def _batch():
+    if "b" not in _cache:
+        from oracle.d3m import D3MOracle
+        from paper_2002_05018_amd import Solver
+        probs = W.make_batch_config(seed=11, count=3, n_range=(4, 7), nrhs=3)
+        print(f"[gpu batch] n={[p.n for p in probs]} subdomains={[p.n_sub for p in probs]}", flush=True)
+        s = Solver.batch(probs, probs[0].k, probs[0].alpha)
+        f = s.rhs_planewave_batch(np.stack([p.dirs for p in probs]), np.stack([p.pols for p in probs]))
+        _, eo, _ = s.layout()
+        ref = []
+        for p, prob in enumerate(probs):
+            fp = f[:, eo[p]:eo[p + 1]]
+            ref.append(D3MOracle.from_problem(prob).factor().solve(fp))
+        _cache["b"] = (probs, s, f, eo, ref)
+    return _cache["b"]
+
+
+def test_batch_fp64_matches_oracle_per_problem():
+    probs, s, f, eo, ref = _batch()
+    s.factor("fp64")
+    E, info = s.solve(torch.from_numpy(f).cuda(), with_info=True)
+    E = E.cpu().numpy()
+    assert info["residual"] <= 1e-11
+    for p in range(len(probs)):
+        assert _rel(E[:, eo[p]:eo[p + 1]], ref[p]) <= 1e-10, p
+
+
+def test_batch_fp32_refinement_per_problem():
+    probs, s, f, eo, ref = _batch()
+    s.factor("fp32_ir")
+    E, info = s.solve(torch.from_numpy(f).cuda(), with_info=True)
+    assert info["converged"] and info["residual"] <= 1e-10
+    E = E.cpu().numpy()
+    for p in range(len(probs)):
+        assert _rel(E[:, eo[p]:eo[p + 1]], ref[p]) <= 1e-9, p
+
+
+def test_batch_scaled_problem_alone_differs_only_by_scale():
+    """A problem of the batch is the unit cube at k = 2 pi n / 8 rescaled by
+    s = n / 8, and its system is the unit-cube system divided by s (every
+    term of the edge-element system scales alike), so with the same load the
+    unit-cube field is the batch field divided by s."""
+    from paper_2002_05018_amd import Solver
+    probs, s, f, eo, ref = _batch()
+    prob = probs[0]
+    sc = prob.n / 8.0
+    unit = W.Problem("unit", prob.n, prob.parts, prob.xyz / sc, prob.tets, prob.part, prob.eps_r,
+                     prob.k * sc, -1j * prob.k * sc, prob.dirs, prob.pols)
+    u = Solver.from_problem(unit)
+    u.factor("fp64")
+    fp = np.ascontiguousarray(f[:, eo[0]:eo[1]])
+    Eu = u.solve(torch.from_numpy(fp).cuda()).cpu().numpy()
+    assert _rel(Eu, ref[0] / sc) <= 1e-10
+
+
+def test_graph_replays_match_eager_bitwise():
+    from paper_2002_05018_amd import Solver
+    prob = W.make_problem(4, (2, 2, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=5, seed=21)
+    eager = Solver.from_problem(prob)
+    graph = Solver.from_problem(prob, use_graph=True)
+    f = torch.from_numpy(eager.rhs_planewave(prob.dirs, prob.pols)).cuda()
+    eager.factor("fp64")
+    want = eager.solve(f).cpu().numpy()
+    fbuf = f.clone()
+    out = torch.empty_like(f)
+    for rep in range(3):
+        graph.factor("fp64")  # capture on the first call, replay afterwards
+        for scale in (1.0, 2.0):
+            fbuf.copy_(f * scale)  # eager work between replays, same buffer
+            torch.cuda.synchronize()
+            graph.solve(fbuf, out=out)
+            got = out.cpu().numpy()
+            assert np.array_equal(got, want * scale), (rep, scale)
+    # FP32 factors with refinement through graphs (the refinement loop itself is eager)
+    graph.factor("fp32_ir")
+    eager.factor("fp32_ir")
+    Eg, ig = graph.solve(f, with_info=True)
+    Ee, ie = eager.solve(f, with_info=True)
+    assert ig["iterations"] == ie["iterations"]
+    assert np.array_equal(Eg.cpu().numpy(), Ee.cpu().numpy())
+
+
+@pytest.mark.parametrize("tune", [{"s1_block": 1}, {"s1_block": 4}, {"lookahead_tasks": 1},
+                                  {"solve_cols": 16}])
+def test_tuning_variants_agree(tune):
+    from paper_2002_05018_amd import Solver
+    prob = W.make_problem(5, (2, 2, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=40, seed=22)
+    s = Solver.from_problem(prob)
+    f = torch.from_numpy(s.rhs_planewave(prob.dirs, prob.pols)).cuda()
+    s.factor("fp64")
+    want = s.solve(f).cpu().numpy()
+    s.set_tuning(**tune)
+    s.factor("fp64")
+    got, info = s.solve(f, with_info=True)
+    assert info["residual"] <= 1e-11
+    assert _rel(got.cpu().numpy(), want) <= 1e-12
+
+
+def test_autotune_picks_a_valid_tuning():
+    from paper_2002_05018_amd import Solver, autotune
+    prob = W.make_problem(4, (2, 2, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=20, seed=23)
+    s = Solver.from_problem(prob)
+    f = torch.from_numpy(s.rhs_planewave(prob.dirs, prob.pols)).cuda()
+    s.factor("fp64")
+    want = s.solve(f).cpu().numpy()
+    res = autotune(s, f, "fp64", repeats=1)
+    assert not res["cached"] and len(res["trials"]) == 8
+    assert s.tuning() == res["tuning"]
+    s.factor("fp64")
+    assert _rel(s.solve(f).cpu().numpy(), want) <= 1e-12

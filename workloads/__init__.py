@@ -163,7 +163,7 @@ def make_problem(n, parts=(1, 1, 1), *, eps="one", k=2 * math.pi, nrhs=1,
 CONFIGS = {
     1: "6^3 hexes, 2x2x1 boxes, eps_r = 1, k = 2*pi, 1 RHS (+z, x-polarised)",
     2: "24^3 hexes, 4x4x4 boxes, eps_r ~ U[1,4], k = 6*pi, 8 RHS",
-    3: "32 independent problems, 12^3..32^3 hexes, jittered boxes, eps_r ~ U[1,4], 16 RHS each",
+    3: "32 independent problems, 12^3..32^3 hexes of side 1/8, jittered boxes, eps_r ~ U[1,4], k = 2*pi, 16 RHS each",
     4: "48^3 hexes, 8x8x8 boxes, eps_r = clip(lognormal(0.5, 0.3), 1, 10), k = 12*pi, 32 RHS",
     5: "32^3 hexes, 4x4x4 boxes, dielectric sphere r = 0.3 (eps_r ~ U[1,6] inside), k = 4*pi, 4 RHS, 64 receivers",
 }
@@ -224,16 +224,22 @@ def make_config(i: int, seed: int | None = None) -> Problem:
     raise ValueError(f"unknown configuration {i}")
 
 
-def make_batch_config(seed: int = 3, count: int = 32, n_range=(12, 32), nrhs=16):
-    """Configuration 3: ``count`` independent cube problems.
+def make_batch_config(seed: int = 3, count: int = 32, n_range=(12, 32), nrhs=16, hex_size=0.125):
+    """Configuration 3: ``count`` independent cube problems at one frequency.
 
     n ~ U{n_range}; boxes per axis p = clip(ceil(n/8), 2, 4); box cuts at
     round(b*n/p) plus a seeded jitter in {-1, 0, +1} (keeping >= 2 hexes per
-    box); eps_r ~ U[1, 4]; k = 2*pi*n/8 (eight hexes per free-space
-    wavelength); ``nrhs`` plane waves each.
+    box); eps_r ~ U[1, 4]; ``nrhs`` plane waves each.  Every cube has hexes
+    of side ``hex_size`` (1/8: eight hexes per free-space wavelength at
+    k = 2*pi), so problem b is a cube of side n*hex_size wavelengths.  This is
+    the unit cube at k = 2*pi*n/8 rescaled by n/8: stiffness, mass, absorbing
+    and Robin terms of the edge-element system all scale by the same factor,
+    so the two systems differ by one scalar and have the same solution up to
+    that factor.  A shared k lets the problems be factored as one batch.
     """
     rng = np.random.default_rng(seed)
     ns = rng.integers(n_range[0], n_range[1] + 1, size=count)
+    k = 2 * math.pi
     probs = []
     for b, n in enumerate(ns):
         n = int(n)
@@ -251,10 +257,10 @@ def make_batch_config(seed: int = 3, count: int = 32, n_range=(12, 32), nrhs=16)
                 c[m] = min(c[m], c[m + 1] - 2)
             cuts.append(c)
         xyz, tets = kuhn_cube_mesh(n)
+        xyz = xyz * (n * hex_size)
         part = box_partition(n, (p, p, p), cuts)
         eps_r = rng.uniform(1.0, 4.0, tets.shape[0])
         dirs, pols = _draw_plane_waves(rng, nrhs)
-        k = 2 * math.pi * n / 8
         probs.append(Problem(f"cfg3[{b}]", n, (p, p, p), xyz, tets, part, eps_r,
                              k, -1j * k, dirs, pols))
     return probs
