@@ -237,6 +237,10 @@ int d3m_query(d3m_handle h, d3m_info *info);
 void d3m_destroy(d3m_handle h);
 const char *d3m_last_error(void);
 
+/* Switch opt.use_graph for later calls (0 drops the captured graphs).
+ * Errors: D3M_EINVAL. */
+int d3m_set_graphs(d3m_handle h, int use_graph);
+
 /* Launch-shape choices of the schedules; paper_2002_05018_amd.autotune picks
  * them by timing.  Zero selects the default. */
 typedef struct {

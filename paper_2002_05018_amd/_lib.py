@@ -41,7 +41,7 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
-                    "d3m_get_tuning", "d3m_set_tuning"]
+                    "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"]
 
 
 class d3m_c128(C.Structure):
@@ -94,6 +94,7 @@ _lib.d3m_setup_batch.argtypes = [C.POINTER(d3m_batch_item), C.c_int32, C.c_doubl
 _lib.d3m_batch_layout.argtypes = [_h, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.d3m_rhs_planewave_batch.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
                                          C.c_void_p]
+_lib.d3m_set_graphs.argtypes = [_h, C.c_int]
 _lib.d3m_get_tuning.argtypes = [_h, C.POINTER(d3m_tuning)]
 _lib.d3m_set_tuning.argtypes = [_h, C.POINTER(d3m_tuning)]
 _lib.d3m_update_eps.argtypes = [_h, C.POINTER(C.c_double)]
@@ -113,7 +114,7 @@ _lib.d3m_debug_export.restype = C.c_int64
 _lib.d3m_set_profile.argtypes = [_h, C.c_int]
 for _f in ("d3m_setup", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch", "d3m_update_eps",
            "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
-           "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning"):
+           "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -310,6 +311,10 @@ class Solver:
         inf = d3m_info()
         _check(_lib.d3m_query(self._handle, C.byref(inf)))
         return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name != "reserved"}
+
+    def set_graphs(self, use_graph):
+        """Replay captured HIP graphs (True) or launch eagerly (False) from now on."""
+        _check(_lib.d3m_set_graphs(self._handle, int(bool(use_graph))))
 
     TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks")
 

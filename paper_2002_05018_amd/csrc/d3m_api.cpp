@@ -800,6 +800,14 @@ int d3m_set_profile(d3m_handle h, int level) {
     return D3M_OK;
 }
 
+int d3m_set_graphs(d3m_handle h, int use_graph) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (use_graph != 0 && use_graph != 1) return fail(D3M_EINVAL, "use_graph must be 0 or 1");
+    if (!use_graph) h->drop_graphs();
+    h->opt.use_graph = use_graph;
+    return D3M_OK;
+}
+
 int d3m_get_tuning(d3m_handle h, d3m_tuning *t) {
     if (!h || !t) return fail(D3M_EINVAL, "null argument");
     *t = h->tune;
