@@ -252,10 +252,14 @@ typedef struct {
     int32_t lookahead_tasks; /* an elimination step whose updates off the
                                 next step's columns number at least this many
                                 tasks runs them on a second stream (512)     */
-    int32_t reserved[5];
+    int32_t k_block;         /* longest chain of pivot units of K (each the
+                                only child of the next in the elimination
+                                tree) whose updates beyond the chain are
+                                applied together (default 2, at most 16)     */
+    int32_t reserved[4];
 } d3m_tuning;
 
-/* Read / replace the tuning.  A new s1_block rebuilds the factor schedule
+/* Read / replace the tuning.  A new s1_block or k_block rebuilds the factor schedule
  * (the storage layout is unchanged) and invalidates the factors; any change
  * drops captured graphs.  Errors: D3M_EINVAL (value out of range). */
 int d3m_get_tuning(d3m_handle h, d3m_tuning *t);

@@ -7,6 +7,8 @@ launch shapes the schedules expose:
 * ``s1_block``: tile columns of a subdomain matrix whose Schur updates beyond
   them are applied together (the depth of the blocked update, i.e. how many
   64x64 tile products one work-group accumulates per target tile);
+* ``k_block``: the same depth for chains of pivot units of K in the
+  elimination tree;
 * ``lookahead_tasks``: how many off-critical update tasks an elimination step
   needs before they are moved to the second stream;
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
@@ -26,11 +28,12 @@ __all__ = ["DEFAULT_SPACE", "signature", "autotune"]
 
 DEFAULT_SPACE = {
     "s1_block": (2, 1, 4),
+    "k_block": (2, 1, 4, 8),
     "lookahead_tasks": (512, 128, 2048),
     "solve_cols": (32, 16),
 }
 # parameters that change the factorisation schedule (the rest only the solve)
-_FACTOR_KEYS = ("s1_block", "lookahead_tasks")
+_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks")
 
 
 def signature(solver, nrhs, precision) -> str:

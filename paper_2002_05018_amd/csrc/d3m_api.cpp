@@ -741,7 +741,7 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
         if (!sub_group.empty() && (int)sub_group.size() != h->dc.N)
             throw Error{-1, "a problem of the batch has an empty subdomain"};
         order_blocks(h->bo, h->dc, h->mesh, sub_group);
-        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block);
+        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block, 0);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {
@@ -820,14 +820,15 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     if (t->solve_cols != 0 && t->solve_cols != 16 && t->solve_cols != 32)
         return fail(D3M_EINVAL, "solve_cols must be 0, 16 or 32");
     if (t->lookahead_tasks < 0) return fail(D3M_EINVAL, "lookahead_tasks must be >= 0");
-    const int old_s1 = h->tune.s1_block;
+    if (t->k_block < 0 || t->k_block > 16) return fail(D3M_EINVAL, "k_block must be in [0, 16]");
+    const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block;
     h->drop_graphs();
     h->tune = *t;
-    if (t->s1_block != old_s1) {
+    if (t->s1_block != old_s1 || t->k_block != old_k) {
         // the tile layout does not depend on the blocking: only the schedules change
         Plan np;
         try {
-            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block);
+            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block, t->k_block);
         } catch (const Error &e) {
             return fail(D3M_EINVAL, e.msg);
         } catch (const std::bad_alloc &) {

@@ -22,8 +22,9 @@ inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total -
 
 }  // namespace
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block) {
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block) {
     const int S1_BLOCK = std::max(1, std::min(16, s1_block > 0 ? s1_block : 2));
+    const int K_BLOCK = std::max(1, std::min(16, k_block > 0 ? k_block : 2));
     const int N = dc.N;
     pl = Plan();
 
@@ -330,6 +331,29 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     // ------------------------------------- step 5 (block LDL^T of -K) plan --
     std::vector<std::vector<int>> by_level(nlev);
     for (int j = 0; j < nb; ++j) by_level[ulevel[j]].push_back(j);
+    // Chain blocking of the trailing updates (the tree analogue of S1_BLOCK):
+    // consecutive units of an elimination-tree chain (each the only child of
+    // the next), at most K_BLOCK long, form a segment.  A unit updates the
+    // columns of the later units of its segment at once (the next one needs
+    // them); its updates of every column beyond the segment are delayed to
+    // the step of the segment's last unit, which applies the pairs of all the
+    // segment's units together (one read-modify-write of each target per
+    // segment).  Every column k beyond the segment belongs to an ancestor of
+    // the segment's last unit, so its updates still land before its step.
+    std::vector<int> nchild(nb, 0), seg_last(nb), seg_len(nb, 1), seg_of(nb);
+    for (int j = 0; j < nb; ++j)
+        if (!ustruct[j].empty()) nchild[ustruct[j][0]]++;
+    for (int j = 0; j < nb; ++j) seg_of[j] = j;
+    for (int j = 0; j < nb; ++j) {
+        if (ustruct[j].empty()) continue;
+        const int p = ustruct[j][0];
+        if (nchild[p] == 1 && seg_len[seg_of[j]] < K_BLOCK) {
+            seg_of[p] = seg_of[j];
+            seg_len[seg_of[j]]++;
+        }
+    }
+    for (int j = 0; j < nb; ++j) seg_last[seg_of[j]] = j;  // units of a segment increase along the chain
+    std::vector<std::vector<int>> delayed(nb);  // per segment end: units whose updates it applies
     const int LDS_MAX_N = 136;
     for (int L = 0; L < nlev; ++L) {
         const auto &J = by_level[L];
@@ -386,10 +410,21 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         // updates grouped by target block so that every target tile is
         // written by exactly one work-group (deterministic, atomic-free)
         std::map<std::pair<int, int>, std::vector<int>> targets;
-        for (int j : J)
+        for (int j : J) {
+            const int f = seg_last[seg_of[j]];
             for (size_t x = 0; x < ustruct[j].size(); ++x)
-                for (size_t y = 0; y <= x; ++y)
-                    targets[{ustruct[j][x], ustruct[j][y]}].push_back(j);
+                for (size_t y = 0; y <= x; ++y) {
+                    const int k = ustruct[j][y];
+                    if (f == j || k <= f) targets[{ustruct[j][x], k}].push_back(j);
+                }
+            if (f != j) delayed[f].push_back(j);
+        }
+        for (int f : J)
+            for (int j : delayed[f])  // columns beyond the segment, from its earlier units
+                for (size_t x = 0; x < ustruct[j].size(); ++x)
+                    for (size_t y = 0; y <= x; ++y)
+                        if (ustruct[j][y] > f) targets[{ustruct[j][x], ustruct[j][y]}].push_back(j);
+        for (auto &kv : targets) std::sort(kv.second.begin(), kv.second.end());
         // targets in block columns of the next level first
         st.up0 = (i64)pl.gemm.size();
         for (int pass = 0; pass < 2; ++pass) {

@@ -8,8 +8,9 @@
 * Graph replays (opt.use_graph) must reproduce the eager launches bit for
   bit, replay after replay, with eager work and synchronisations between the
   replays and new right-hand-side values in the same buffer.
-* Other launch shapes (blocked-update depth, solve column block, look-ahead
-  threshold) change only the summation order: results agree to 1e-12.
+* Other launch shapes (blocked-update depths of the subdomain and K phases,
+  solve column block, look-ahead threshold) change only the summation
+  order: results agree to 1e-12.
 """
 import numpy as np
 import pytest
@@ -109,8 +110,8 @@ def test_graph_replays_match_eager_bitwise():
     assert np.array_equal(Eg.cpu().numpy(), Ee.cpu().numpy())
 
 
-@pytest.mark.parametrize("tune", [{"s1_block": 1}, {"s1_block": 4}, {"lookahead_tasks": 1},
-                                  {"solve_cols": 16}])
+@pytest.mark.parametrize("tune", [{"s1_block": 1}, {"s1_block": 4}, {"k_block": 1}, {"k_block": 8},
+                                  {"lookahead_tasks": 1}, {"solve_cols": 16}])
 def test_tuning_variants_agree(tune):
     from paper_2002_05018_amd import Solver
     prob = W.make_problem(5, (2, 2, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=40, seed=22)
@@ -133,7 +134,7 @@ def test_autotune_picks_a_valid_tuning():
     s.factor("fp64")
     want = s.solve(f).cpu().numpy()
     res = autotune(s, f, "fp64", repeats=1)
-    assert not res["cached"] and len(res["trials"]) == 8
+    assert not res["cached"] and len(res["trials"]) == 12
     assert s.tuning() == res["tuning"]
     s.factor("fp64")
     assert _rel(s.solve(f).cpu().numpy(), want) <= 1e-12
