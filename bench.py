@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=32, help="problems of the configuration 3 batch")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shapes instead of the autotuner's choice")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2002_05018_amd", "tuning_mi355x.json"),
+                    help="autotuner results by problem signature (a stored entry is applied without timing)")
     ap.add_argument("--cpu-sample-subdomains", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (scale for HBM counters)")
@@ -144,7 +148,7 @@ def bench_batch(args):
                                                     np.stack([p.pols for p in probs]))).cuda()
     E = torch.empty_like(f)
     t0 = time.perf_counter()
-    tuned = autotune(solver, f, FP64, repeats=1,
+    tuned = autotune(solver, f, FP64, repeats=1, cache=args.tune_cache,
                      log=lambda m: print(m, file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
     ms, wall_ms = timed_steps(solver, FP64, f, E, args.steps, args.warmup, torch)
@@ -214,6 +218,14 @@ def main():
     f = torch.from_numpy(f_host).cuda()
     E = torch.empty_like(f)
     torch.cuda.synchronize()
+    # launch shapes chosen by the autotuner (untimed), per precision
+    tuning = {}
+    tune_s = 0.0
+    if not args.no_autotune:
+        from paper_2002_05018_amd import autotune
+        t0 = time.perf_counter()
+        tuning["fp64"] = autotune(solver, f, FP64, cache=args.tune_cache)["tuning"]
+        tune_s += time.perf_counter() - t0
 
     ms, wall_ms = timed_steps(solver, FP64, f, E, args.steps, args.warmup, torch)
     up = solver.kernel_stats("update_gemm")
@@ -272,6 +284,10 @@ def main():
     result["factor_TFLOPs"] = result["algorithmic_flops_factor"] / (ms * 1e-3) / 1e12
 
     if not args.no_fp32:
+        if not args.no_autotune:
+            t0 = time.perf_counter()
+            tuning["fp32_ir"] = autotune(solver, f, FP32_IR, cache=args.tune_cache)["tuning"]
+            tune_s += time.perf_counter() - t0
         ms32, _ = timed_steps(solver, FP32_IR, f, E, args.steps, args.warmup, torch)
         up32 = solver.kernel_stats("update_gemm")
         _, sinfo32 = solver.solve(f, out=E, with_info=True)
@@ -281,6 +297,8 @@ def main():
                              "speedup_vs_fp64": ms / ms32,
                              "roofline": {"bound": "mfma", "achieved": ach32, "peak": MFMA_PEAK["c64"],
                                           "unit": "TFLOP/s", "frac": ach32 / MFMA_PEAK["c64"]}}
+    result["config"]["tuning"] = tuning or "defaults"
+    result["autotune_s"] = tune_s
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample_subdomains)
     print(json.dumps(result))

@@ -256,7 +256,11 @@ typedef struct {
                                 only child of the next in the elimination
                                 tree) whose updates beyond the chain are
                                 applied together (default 2, at most 16)     */
-    int32_t reserved[4];
+    int32_t side_early;      /* 1: a step's second-stream updates start as
+                                soon as its panels are done; 0 (default):
+                                after its critical updates, so that the next
+                                pivot launch finds free compute units        */
+    int32_t reserved[3];
 } d3m_tuning;
 
 /* Read / replace the tuning.  A new s1_block or k_block rebuilds the factor schedule

@@ -11,6 +11,8 @@ launch shapes the schedules expose:
   elimination tree;
 * ``lookahead_tasks``: how many off-critical update tasks an elimination step
   needs before they are moved to the second stream;
+* ``side_early``: whether those start right after the step's panels or only
+  after its critical updates;
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
   (16 or 32 columns of the MFMA tile).
 
@@ -30,10 +32,12 @@ DEFAULT_SPACE = {
     "s1_block": (2, 1, 4),
     "k_block": (2, 1, 4, 8),
     "lookahead_tasks": (512, 128, 2048),
+    "side_early": (0, 1),
     "solve_cols": (32, 16),
 }
+_PREC = {0: "fp64", 1: "fp32_ir", "fp64": "fp64", "fp32_ir": "fp32_ir"}
 # parameters that change the factorisation schedule (the rest only the solve)
-_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks")
+_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early")
 
 
 def signature(solver, nrhs, precision) -> str:
@@ -43,7 +47,7 @@ def signature(solver, nrhs, precision) -> str:
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
     return json.dumps({"n_edges": i["n_edges"], "n_subdomains": i["n_subdomains"], "n_blocks": i["n_blocks"],
                        "n_lm": i["n_lm"], "n_problems": i["n_problems"], "nrhs": int(nrhs),
-                       "precision": str(precision), "device": dev}, sort_keys=True)
+                       "precision": _PREC.get(precision, str(precision)), "device": dev}, sort_keys=True)
 
 
 def _time(fn, repeats):
@@ -115,7 +119,10 @@ def autotune(solver, rhs, precision="fp64", space=None, repeats=2, cache=None, l
     solver.set_tuning(**best)
     if cache:
         store[key] = best
-        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
-        with open(cache, "w") as fh:
-            json.dump(store, fh, indent=1, sort_keys=True)
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(store, fh, indent=1, sort_keys=True)
+        except OSError:
+            pass  # a read-only cache location still serves stored entries
     return {"tuning": best, "trials": trials, "cached": False}

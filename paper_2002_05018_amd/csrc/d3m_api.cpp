@@ -442,14 +442,24 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
         const i64 ncrit = split ? st.ncrit : st.nup;
         const double crit_flops = split ? st.crit_flops : st.up_flops;
         const i64 nrest = st.nup - ncrit;
-        if (nrest > 0) {
-            hipEvent_t scaled = h->sync_event();
-            HIPCHK(hipEventRecord(scaled, s));
-            HIPCHK(hipStreamWaitEvent(s2, scaled, 0));
-            h->prof_begin(KID_UPDATE, ev, s2);
+        // side launch: after the critical updates, so that the next pivot
+        // launch is dispatched before the side work fills the machine (a
+        // pivot work-group sharing compute units with update waves runs its
+        // sequential steps 2-3x slower), or (side_early) right after the
+        // panels it reads
+        auto launch_rest = [&]() -> int {
+            hipEvent_t ready = h->sync_event();
+            HIPCHK(hipEventRecord(ready, s));
+            HIPCHK(hipStreamWaitEvent(s2, ready, 0));
+            hipEvent_t e2{};
+            h->prof_begin(KID_UPDATE, e2, s2);
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + ncrit, nrest, h->d_pairs, b, 1, s2));
-            h->prof_end(KID_UPDATE, ev, st.up_flops - crit_flops, s2);
-        }
+            h->prof_end(KID_UPDATE, e2, st.up_flops - crit_flops, s2);
+            return D3M_OK;
+        };
+        const bool late = h->tune.side_early == 0;
+        int rc;
+        if (nrest > 0 && !late && (rc = launch_rest()) != D3M_OK) return rc;
         if (rest_done && st.wait_rest) {
             HIPCHK(hipStreamWaitEvent(s, rest_done, 0));
             rest_done = nullptr;
@@ -459,6 +469,7 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
             HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, ncrit, h->d_pairs, b, 1, s));
             h->prof_end(KID_UPDATE, ev, crit_flops, s);
         }
+        if (nrest > 0 && late && (rc = launch_rest()) != D3M_OK) return rc;
         if (nrest > 0) {  // (a step with side updates always waited above, so nothing is lost)
             rest_done = h->sync_event();
             HIPCHK(hipEventRecord(rest_done, s2));
@@ -821,6 +832,7 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
         return fail(D3M_EINVAL, "solve_cols must be 0, 16 or 32");
     if (t->lookahead_tasks < 0) return fail(D3M_EINVAL, "lookahead_tasks must be >= 0");
     if (t->k_block < 0 || t->k_block > 16) return fail(D3M_EINVAL, "k_block must be in [0, 16]");
+    if (t->side_early != 0 && t->side_early != 1) return fail(D3M_EINVAL, "side_early must be 0 or 1");
     const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block;
     h->drop_graphs();
     h->tune = *t;

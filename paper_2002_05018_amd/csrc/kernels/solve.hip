@@ -118,17 +118,23 @@ __device__ __forceinline__ void sv_mma(typename Mfma<T>::acc (&re)[NCB], typenam
 // Forward: y = TT x (TT = L^{-1} P^T of the block), v = D^{-1} y (2x2 pivots
 // never cross the tile).  Backward: x = TT^T (v - acc) (= P L^{-T} (v - acc)).
 // xsp is a free LDS buffer.
+// lf: this thread's fragment of TT (forward) or TT^T (backward), loaded by
+// the caller.
 template <typename T, bool BWD, int NCB>
-__device__ __forceinline__ void sv_diag(const VDiagTask &tk, int c0, int ncol, const Bases &b, const VBases &vb,
-                                        const DArrays &D, int nrhs, const typename C2T<T>::type *xin,
-                                        typename C2T<T>::type *xsp) {
+__device__ __forceinline__ void sv_diag(const typename C2T<T>::type (&lf)[16], const VDiagTask &tk, int c0,
+                                        int ncol, const VBases &vb, const DArrays &D, int nrhs,
+                                        const typename C2T<T>::type *xin, typename C2T<T>::type *xsp) {
     using M = Mfma<T>;
     using T2 = typename C2T<T>::type;
     using acc_t = typename M::acc;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int m = 16 * (threadIdx.x >> 6) + li;
-    T2 lf[16];
-    sv_load_l<T2, BWD>(lf, enc_ptr<T2>(b, tk.tt));
+    // pivot data of this row (forward), loaded ahead of the product
+    const int64_t dr = tk.drow + m;
+    const bool live = !BWD && m < tk.n;
+    const double2 di = live ? D.dinv[dr] : make_double2(0, 0);
+    const int pv = live ? D.piv[dr] : 0;
+    const double2 dio = pv ? D.dinvoff[dr] : make_double2(0, 0);
     acc_t re[NCB], im[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
@@ -145,11 +151,6 @@ __device__ __forceinline__ void sv_diag(const VDiagTask &tk, int c0, int ncol, c
     if (BWD) return;
     __syncthreads();
     T2 *v = vptr<T2>(vb, tk.v, nrhs) + (int64_t)c0 * 64;
-    const int64_t dr = tk.drow + m;
-    const bool live = m < tk.n;
-    const double2 di = live ? D.dinv[dr] : make_double2(0, 0);
-    const int pv = live ? D.piv[dr] : 0;
-    const double2 dio = pv ? D.dinvoff[dr] : make_double2(0, 0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -173,14 +174,15 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int6
     const VDiagTask tk = tasks[task];
     const int c0 = blockIdx.y * 16 * NCB;
     const int ncol = min(16 * NCB, nrhs - c0);
-    T2 xr[4 * NCB];
+    T2 xr[4 * NCB], lf[16];
     if (BWD)
         sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.v, nrhs), tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr, c0, ncol);
     else
         sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.x, nrhs), nullptr, c0, ncol);
+    sv_load_l<T2, BWD>(lf, enc_ptr<T2>(b, tk.tt));
     sv_put_x<T2, NCB>(sm.xs[0], xr);
     __syncthreads();
-    sv_diag<T, BWD, NCB>(tk, c0, ncol, b, vb, D, nrhs, sm.xs[0], sm.xs[1]);
+    sv_diag<T, BWD, NCB>(lf, tk, c0, ncol, vb, D, nrhs, sm.xs[0], sm.xs[1]);
 }
 
 // Diagonal blocks of several tiles (blocks larger than 64 factored whole):
@@ -295,11 +297,17 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
     acc_t re[NCB], im[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
+    VDiagTask dg{};
+    if (fz >= 0) dg = vdiag[fz];
+    // lf holds the fragment of the next product; after the last one it takes
+    // the fused diagonal solve's TT, whose loads then overlap the last product
     T2 lf[16], xr[4 * NCB];
     if (tk.np > 0) {
         const VUpdPair pr = pairs[tk.p0];
         sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
         sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
+    } else if (fz >= 0) {
+        sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
     }
     for (int p = 0; p < tk.np; ++p) {
         T2 *xs = sm.xs[p & 1];
@@ -312,16 +320,14 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
             const VUpdPair pr = pairs[tk.p0 + p + 1];
             sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
             sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
+        } else if (fz >= 0) {
+            sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
         }
         sv_mma<T, NCB>(re, im, lc, xs);
     }
     T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
-    VDiagTask dg{};
     const T2 *vin = nullptr;
-    if (fz >= 0) {
-        dg = vdiag[fz];
-        if (TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
-    }
+    if (fz >= 0 && TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
     // the buffer not read by the last product (its previous readers passed the last barrier)
     T2 *xd = sm.xs[tk.np & 1];
 #pragma unroll
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
         }
     if (fz < 0) return;
     __syncthreads();
-    sv_diag<T, TR, NCB>(dg, c0, ncol, b, vb, D, nrhs, xd, sm.xs[(tk.np + 1) & 1]);
+    sv_diag<T, TR, NCB>(lf, dg, c0, ncol, vb, D, nrhs, xd, sm.xs[(tk.np + 1) & 1]);
 }
 
 // XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
