@@ -238,6 +238,7 @@ def main():
     upp = solver.kernel_stats("update_gemm")
     solver.set_profile(1)
     _, sinfo = solver.solve(f, out=E, with_info=True)
+    E64 = E.clone()  # FP64 solution: reference for the FP32 form's error
     achieved = up["flops"] / (up["total_ms"] * 1e-3) / 1e12 if up["total_ms"] > 0 else 0.0
     n_launch = up["launches"] / max(args.steps, 1)
     solve_ms = sol["total_ms"] / max(sol["launches"], 1)
@@ -291,9 +292,11 @@ def main():
         ms32, _ = timed_steps(solver, FP32_IR, f, E, args.steps, args.warmup, torch)
         up32 = solver.kernel_stats("update_gemm")
         _, sinfo32 = solver.solve(f, out=E, with_info=True)
+        err32 = float(torch.linalg.vector_norm(E - E64) / torch.linalg.vector_norm(E64))
         ach32 = up32["flops"] / (up32["total_ms"] * 1e-3) / 1e12 if up32["total_ms"] > 0 else 0.0
         result["fp32_ir"] = {"ms_per_step": ms32, "value": ms32 / 1e3, "iterations": sinfo32["iterations"],
                              "relative_residual": sinfo32["residual"],
+                             "rel_error_vs_fp64": err32,
                              "speedup_vs_fp64": ms / ms32,
                              "roofline": {"bound": "mfma", "achieved": ach32, "peak": MFMA_PEAK["c64"],
                                           "unit": "TFLOP/s", "frac": ach32 / MFMA_PEAK["c64"]}}

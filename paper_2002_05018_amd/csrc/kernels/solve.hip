@@ -90,15 +90,54 @@ template <typename T2, int NCB> __device__ __forceinline__ void sv_put_x(T2 *xs,
     }
 }
 
+// Accumulators of a solve product (out^T layout of the MFMA).  FP64 factors
+// accumulate in FP64 MFMA registers.  FP32 factors use FP32 MFMAs over 16
+// inner indices at a time and add each partial sum into FP64 registers, so
+// the rounding of a long sum does not add to the refinement's work (the
+// vectors are still stored in FP32).
+template <typename T, int NCB> struct SvAcc;
+template <int NCB> struct SvAcc<double, NCB> {
+    d4_t re[NCB], im[NCB];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = d4_t{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ double2 get(int cb, int r) const { return make_double2(re[cb][r], im[cb][r]); }
+};
+template <int NCB> struct SvAcc<float, NCB> {
+    f4_t re[NCB], im[NCB];
+    d4_t dre[NCB], dim[NCB];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            re[cb] = im[cb] = f4_t{0, 0, 0, 0};
+            dre[cb] = dim[cb] = d4_t{0, 0, 0, 0};
+        }
+    }
+    __device__ __forceinline__ void flush() {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                dre[cb][r] += (double)re[cb][r];
+                dim[cb][r] += (double)im[cb][r];
+            }
+            re[cb] = im[cb] = f4_t{0, 0, 0, 0};
+        }
+    }
+    __device__ __forceinline__ double2 get(int cb, int r) const { return make_double2(dre[cb][r], dim[cb][r]); }
+};
+
 // acc += (op(L) X)^T for the fragment lf and the staged block xs
 template <typename T, int NCB>
-__device__ __forceinline__ void sv_mma(typename Mfma<T>::acc (&re)[NCB], typename Mfma<T>::acc (&im)[NCB],
-                                       const typename C2T<T>::type (&lf)[16], const typename C2T<T>::type *xs) {
+__device__ __forceinline__ void sv_mma(SvAcc<T, NCB> &acc, const typename C2T<T>::type (&lf)[16],
+                                       const typename C2T<T>::type *xs) {
     using M = Mfma<T>;
     using T2 = typename C2T<T>::type;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int kg = 0; kg < 4; ++kg)
+    for (int kg = 0; kg < 4; ++kg) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int q = 16 * kg + 4 * lk + s;
@@ -106,12 +145,14 @@ __device__ __forceinline__ void sv_mma(typename Mfma<T>::acc (&re)[NCB], typenam
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
                 const T2 ax = xs[(16 * cb + li) * SV_PQ + q];
-                re[cb] = M::mma(ax.x, bl.x, re[cb]);
-                im[cb] = M::mma(ax.x, bl.y, im[cb]);
-                re[cb] = M::mma(-ax.y, bl.y, re[cb]);
-                im[cb] = M::mma(ax.y, bl.x, im[cb]);
+                acc.re[cb] = M::mma(ax.x, bl.x, acc.re[cb]);
+                acc.im[cb] = M::mma(ax.x, bl.y, acc.im[cb]);
+                acc.re[cb] = M::mma(-ax.y, bl.y, acc.re[cb]);
+                acc.im[cb] = M::mma(ax.y, bl.x, acc.im[cb]);
             }
         }
+        acc.flush();
+    }
 }
 
 // Diagonal solve of a one-tile block from the input staged in xin.
@@ -126,7 +167,6 @@ __device__ __forceinline__ void sv_diag(const typename C2T<T>::type (&lf)[16], c
                                         const typename C2T<T>::type *xin, typename C2T<T>::type *xsp) {
     using M = Mfma<T>;
     using T2 = typename C2T<T>::type;
-    using acc_t = typename M::acc;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int m = 16 * (threadIdx.x >> 6) + li;
     // pivot data of this row (forward), loaded ahead of the product
@@ -135,18 +175,18 @@ __device__ __forceinline__ void sv_diag(const typename C2T<T>::type (&lf)[16], c
     const double2 di = live ? D.dinv[dr] : make_double2(0, 0);
     const int pv = live ? D.piv[dr] : 0;
     const double2 dio = pv ? D.dinvoff[dr] : make_double2(0, 0);
-    acc_t re[NCB], im[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
-    sv_mma<T, NCB>(re, im, lf, xin);
+    SvAcc<T, NCB> acc;
+    acc.zero();
+    sv_mma<T, NCB>(acc, lf, xin);
     T2 *out = vptr<T2>(vb, BWD ? tk.x : tk.y, nrhs) + (int64_t)c0 * 64;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = 16 * cb + M::out_row(lk, r);
-            if (c < ncol) out[c * 64 + m] = T2{re[cb][r], im[cb][r]};
-            if (!BWD) xsp[c * SV_PQ + m] = T2{re[cb][r], im[cb][r]};
+            const T2 val = from_d2<T2>(acc.get(cb, r));
+            if (c < ncol) out[c * 64 + m] = val;
+            if (!BWD) xsp[c * SV_PQ + m] = val;
         }
     if (BWD) return;
     __syncthreads();
@@ -283,7 +323,6 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
                                                    DArrays D, int nrhs) {
     using M = Mfma<T>;
     using T2 = typename C2T<T>::type;
-    using acc_t = typename M::acc;
     constexpr bool TR = MODE != 0;
     __shared__ SvSmem<T2, NCB> sm;
     const int64_t task = xcd_task(ntask);
@@ -294,9 +333,8 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
     const int ncol = min(16 * NCB, nrhs - c0);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int m = 16 * (threadIdx.x >> 6) + li;
-    acc_t re[NCB], im[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) re[cb] = im[cb] = acc_t{0, 0, 0, 0};
+    SvAcc<T, NCB> acc;
+    acc.zero();
     VDiagTask dg{};
     if (fz >= 0) dg = vdiag[fz];
     // lf holds the fragment of the next product; after the last one it takes
@@ -323,7 +361,7 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
         } else if (fz >= 0) {
             sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
         }
-        sv_mma<T, NCB>(re, im, lc, xs);
+        sv_mma<T, NCB>(acc, lc, xs);
     }
     T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
     const T2 *vin = nullptr;
@@ -338,15 +376,13 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
             T2 nw{0, 0};
             if (c < ncol) {
                 T2 *o = out + c * 64 + m;
-                if (MODE == 0) nw = T2{(*o).x - re[cb][r], (*o).y - im[cb][r]};
-                else if (MODE == 1) nw = T2{re[cb][r], im[cb][r]};
-                else nw = T2{(*o).x + re[cb][r], (*o).y + im[cb][r]};
+                const double2 res = acc.get(cb, r);
+                if (MODE == 0) nw = from_d2<T2>(csub(to_d2(*o), res));
+                else if (MODE == 1) nw = from_d2<T2>(res);
+                else nw = from_d2<T2>(cadd(to_d2(*o), res));
                 *o = nw;
                 // input of the fused diagonal solve: x (forward) or v - acc (backward)
-                if (TR && fz >= 0) {
-                    const T2 vv = vin[c * 64 + m];
-                    nw = T2{vv.x - nw.x, vv.y - nw.y};
-                }
+                if (TR && fz >= 0) nw = from_d2<T2>(csub(to_d2(vin[c * 64 + m]), to_d2(nw)));
             }
             if (fz >= 0) xd[c * SV_PQ + m] = nw;
         }
