@@ -260,10 +260,14 @@ typedef struct {
                                 soon as its panels are done; 0 (default):
                                 after its critical updates, so that the next
                                 pivot launch finds free compute units        */
-    int32_t reserved[3];
+    int32_t k_fuse;          /* 1: the updates of the next level's columns of
+                                K are applied by that level's pivot and panel
+                                launches (one launch fewer per level) instead
+                                of a separate update launch; default 0       */
+    int32_t reserved[2];
 } d3m_tuning;
 
-/* Read / replace the tuning.  A new s1_block or k_block rebuilds the factor schedule
+/* Read / replace the tuning.  A new s1_block, k_block or k_fuse rebuilds the factor schedule
  * (the storage layout is unchanged) and invalidates the factors; any change
  * drops captured graphs.  Errors: D3M_EINVAL (value out of range). */
 int d3m_get_tuning(d3m_handle h, d3m_tuning *t);

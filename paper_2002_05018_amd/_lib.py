@@ -76,7 +76,8 @@ class d3m_batch_item(C.Structure):
 
 class d3m_tuning(C.Structure):
     _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
-                ("k_block", C.c_int32), ("side_early", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("k_block", C.c_int32), ("side_early", C.c_int32), ("k_fuse", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class d3m_solve_info(C.Structure):
@@ -316,7 +317,7 @@ class Solver:
         """Replay captured HIP graphs (True) or launch eagerly (False) from now on."""
         _check(_lib.d3m_set_graphs(self._handle, int(bool(use_graph))))
 
-    TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early")
+    TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early", "k_fuse")
 
     def tuning(self):
         t = d3m_tuning()
@@ -325,8 +326,8 @@ class Solver:
 
     def set_tuning(self, **kw):
         """Change launch-shape choices (keys of TUNING_KEYS; 0 = default).  A
-        new s1_block or k_block re-plans the factor schedule and drops the
-        factors."""
+        new s1_block, k_block or k_fuse re-plans the factor schedule and
+        drops the factors."""
         t = d3m_tuning()
         _check(_lib.d3m_get_tuning(self._handle, C.byref(t)))
         for k, v in kw.items():

@@ -13,6 +13,8 @@ launch shapes the schedules expose:
   needs before they are moved to the second stream;
 * ``side_early``: whether those start right after the step's panels or only
   after its critical updates;
+* ``k_fuse``: whether the updates of the next level's columns of K get their
+  own launch or are applied inside that level's pivot and panel launches;
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
   (16 or 32 columns of the MFMA tile).
 
@@ -33,11 +35,12 @@ DEFAULT_SPACE = {
     "k_block": (2, 1, 4, 8),
     "lookahead_tasks": (512, 128, 2048),
     "side_early": (0, 1),
+    "k_fuse": (0, 1),
     "solve_cols": (32, 16),
 }
 _PREC = {0: "fp64", 1: "fp32_ir", "fp64": "fp64", "fp32_ir": "fp32_ir"}
 # parameters that change the factorisation schedule (the rest only the solve)
-_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early")
+_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early", "k_fuse")
 
 
 def signature(solver, nrhs, precision) -> str:

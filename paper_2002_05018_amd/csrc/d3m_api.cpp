@@ -422,7 +422,8 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
         hipEvent_t ev{};
         if (st.nbk > 0) {
             h->prof_begin(KID_BK, ev, s);
-            HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, b, h->D, h->d_status, h->d_bkscratch, s));
+            HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, h->d_pairs, b, h->D, h->d_status,
+                                h->d_bkscratch, s));
             h->prof_end(KID_BK, ev, 0.0, s);
         }
         if (st.npan > 0 || st.nsc > 0) {
@@ -752,7 +753,7 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
         if (!sub_group.empty() && (int)sub_group.size() != h->dc.N)
             throw Error{-1, "a problem of the batch has an empty subdomain"};
         order_blocks(h->bo, h->dc, h->mesh, sub_group);
-        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block, 0);
+        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block, 0, false);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {
@@ -833,14 +834,15 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     if (t->lookahead_tasks < 0) return fail(D3M_EINVAL, "lookahead_tasks must be >= 0");
     if (t->k_block < 0 || t->k_block > 16) return fail(D3M_EINVAL, "k_block must be in [0, 16]");
     if (t->side_early != 0 && t->side_early != 1) return fail(D3M_EINVAL, "side_early must be 0 or 1");
-    const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block;
+    if (t->k_fuse != 0 && t->k_fuse != 1) return fail(D3M_EINVAL, "k_fuse must be 0 or 1");
+    const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block, old_f = h->tune.k_fuse;
     h->drop_graphs();
     h->tune = *t;
-    if (t->s1_block != old_s1 || t->k_block != old_k) {
+    if (t->s1_block != old_s1 || t->k_block != old_k || t->k_fuse != old_f) {
         // the tile layout does not depend on the blocking: only the schedules change
         Plan np;
         try {
-            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block, t->k_block);
+            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block, t->k_block, t->k_fuse != 0);
         } catch (const Error &e) {
             return fail(D3M_EINVAL, e.msg);
         } catch (const std::bad_alloc &) {

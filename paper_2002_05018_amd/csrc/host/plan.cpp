@@ -22,7 +22,8 @@ inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total -
 
 }  // namespace
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block) {
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
+                bool k_fuse) {
     const int S1_BLOCK = std::max(1, std::min(16, s1_block > 0 ? s1_block : 2));
     const int K_BLOCK = std::max(1, std::min(16, k_block > 0 ? k_block : 2));
     const int N = dc.N;
@@ -354,6 +355,12 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     }
     for (int j = 0; j < nb; ++j) seg_last[seg_of[j]] = j;  // units of a segment increase along the chain
     std::vector<std::vector<int>> delayed(nb);  // per segment end: units whose updates it applies
+    // With one-tile units, the updates of the next level's columns (the
+    // critical ones) are not launched on their own: the pivot launch of the
+    // next level applies the pairs of its diagonal tile before factoring it,
+    // and its panel launch those of each panel tile before the product.
+    const bool fuse_next = k_fuse && unit_max > 0 && unit_max <= TILE;
+    std::map<std::pair<int, int>, std::vector<GemmPair>> pending;  // (unit k, row unit i) -> pairs
     const int LDS_MAX_N = 136;
     for (int L = 0; L < nlev; ++L) {
         const auto &J = by_level[L];
@@ -368,6 +375,12 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
             t.n = nsz[j];
             t.ldt = (int32_t)((i64)pl.kR[j] * TILE_ELEMS);
             t.status = (int)pl.bk.size();
+            auto pd = pending.find({j, j});
+            if (pd != pending.end()) {
+                t.p0 = (int32_t)pl.pairs.size();
+                t.np = (int32_t)pd->second.size();
+                pl.pairs.insert(pl.pairs.end(), pd->second.begin(), pd->second.end());
+            }
             pl.bk.push_back(t);
             st.bk_maxn = std::max(st.bk_maxn, t.n);
             pl.flops_s3 += 8.0 * (double)t.n * t.n * t.n / 6.0;
@@ -394,6 +407,12 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                         s.xnext = b + 1 < tj ? E(ARR_KX, kslot(j, i, a, b + 1)) : -1;
                         s.drow = pl.drow_k[j] + (i64)b * TILE;
                         s.ncols = tile_rows(nsz[j], b);
+                        auto pd = pending.find({j, i});
+                        if (pd != pending.end()) {
+                            s.q0 = (int32_t)pl.pairs.size();
+                            s.nq = (int32_t)pd->second.size();
+                            pl.pairs.insert(pl.pairs.end(), pd->second.begin(), pd->second.end());
+                        }
                         pl.scale.push_back(s);
                     }
             double pf = 0.0;
@@ -431,6 +450,16 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
             for (auto &kv : targets) {
                 int i = kv.first.first, k = kv.first.second;
                 if ((ulevel[k] == L + 1) != (pass == 0)) continue;
+                if (pass == 0 && fuse_next) {  // applied by the next level's pivot and panel launches
+                    auto &pd = pending[{k, i}];
+                    const int ra = tile_rows(nsz[i], 0), rb = tile_rows(nsz[k], 0);
+                    for (int j : kv.second) {
+                        pd.push_back({E(ARR_KX, kslot(j, i, 0, 0)), E(ARR_KL, kslot(j, k, 0, 0))});
+                        const double f = 8.0 * tile_rows(nsz[j], 0) * (i == k ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                        pl.flops_s3 += f;
+                    }
+                    continue;
+                }
                 for (int b = 0; b < pl.kt[k]; ++b)
                     for (int a = (i == k ? b : 0); a < pl.kt[i]; ++a) {
                         GemmTask g{E(ARR_K, kslot(k, i, a, b)), (int32_t)pl.pairs.size(), 0};

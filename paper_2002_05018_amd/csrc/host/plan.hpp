@@ -88,6 +88,7 @@ struct Plan {
     i64 factor_entries = 0;
 };
 
-void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block);
+void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
+                bool k_fuse);
 
 }  // namespace d3m

@@ -10,6 +10,9 @@ namespace d3m {
 template <typename T> struct C2T;
 template <> struct C2T<double> { using type = double2; };
 template <> struct C2T<float> { using type = float2; };
+template <typename T2> struct T2S;
+template <> struct T2S<double2> { using type = double; };
+template <> struct T2S<float2> { using type = float; };
 
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }

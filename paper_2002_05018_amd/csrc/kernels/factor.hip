@@ -331,8 +331,14 @@ struct BkHead {
     int pad;
 };
 
+// sum_p A_p B_p^T of one task on 4 waves (defined with the GEMM kernels)
+template <typename T>
+__device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases,
+                                              typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]);
+
 template <typename T2, int NW>
-__global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, Bases bases, DArrays D, int *status) {
+__global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, const GemmPair *pairs, Bases bases,
+                                                       DArrays D, int *status) {
     constexpr int NM = 64, RB = NM / NW, SLD = NM + 1;
     typedef double Regs __attribute__((ext_vector_type(2 * RB)));
     __shared__ double2 colA[2][NM], zcA[2][NM], colB[2][NM], zcB[2][NM];
@@ -361,6 +367,39 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, Base
             zv[2 * bb] = i == j ? 1.0 : 0.0;
             zv[2 * bb + 1] = 0.0;
         }
+    }
+    if (tk.np > 0) {
+        // pending updates of the block, A -= sum_p X_p W_p^T (the previous
+        // step's updates of this column): the first four waves form U on
+        // MFMA (the update GEMM's tile product), U goes through LDS, and every
+        // thread takes U(i, s) for i >= s and U(s, i) above the diagonal, so
+        // that both triangles carry the lower one's rounding (U is symmetric:
+        // W = X D^{-1})
+        using T = typename T2S<T2>::type;
+        using M = Mfma<T>;
+        if (t < 256) {
+            typename M::acc ure[2][2], uim[2][2];
+            const GemmTask ut{0, tk.p0, tk.np};
+            gemm_task_acc<T>(ut, pairs, bases, ure, uim);
+            const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        stage[(wc + 16 * q + M::out_row(lk, r)) * SLD + wr + 16 * m + li] =
+                            make_double2(ure[m][q][r], uim[m][q][r]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int bb = 0; bb < RB; ++bb) {
+            const int j = w + NW * bb;
+            const double2 u = lane >= j ? stage[j * SLD + lane] : stage[lane * SLD + j];
+            av[2 * bb] -= u.x;
+            av[2 * bb + 1] -= u.y;
+        }
+        __syncthreads();  // stage is written again at the end
     }
     int vperm = lane, vinv = lane;  // perm[lane] and its inverse
     unsigned long long active = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
@@ -605,6 +644,36 @@ __device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair
     }
 }
 
+// One product A B^T with A staged in LDS (column-major, column stride 65),
+// B from memory; same operand mapping and accumulator layout as gemm_task_acc.
+template <typename T>
+__device__ __forceinline__ void gemm_lds_acc(const typename C2T<T>::type *alds, const typename C2T<T>::type *B,
+                                             typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]) {
+    using T2 = typename C2T<T>::type;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q) { re[m][q] = acc_t{0, 0, 0, 0}; im[m][q] = acc_t{0, 0, 0, 0}; }
+#pragma unroll
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        const int k = k0 + lk;
+        const T2 wq[2] = {B[k * 64 + wc + li], B[k * 64 + wc + 16 + li]};
+        const T2 xm[2] = {alds[k * 65 + wr + li], alds[k * 65 + wr + 16 + li]};
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
+                re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
+                im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
+                im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
+            }
+    }
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
                                                       Bases bases) {
@@ -664,7 +733,30 @@ __global__ __launch_bounds__(256) void panel_scale_kernel(const GemmTask *tasks,
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
     acc_t re[2][2], im[2][2];
-    gemm_task_acc<T>(tk, pairs, bases, re, im);
+    if (sk.nq == 0) {
+        gemm_task_acc<T>(tk, pairs, bases, re, im);
+    } else {
+        // pending updates of the input tile first: A' = A - sum X W^T, staged
+        // in LDS, then X = A' TT^T with A' read from there
+        const GemmTask ut{0, sk.q0, sk.nq};
+        gemm_task_acc<T>(ut, pairs, bases, re, im);
+        const GemmPair pr = pairs[tk.p0];
+        const T2 *A = enc_ptr<T2>(bases, pr.a);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr + 16 * m + li;
+                    const int col = wc + 16 * q + M::out_row(lk, r);
+                    const T2 a = A[col * 64 + row];
+                    xs[col * 65 + row] = T2{a.x - re[m][q][r], a.y - im[m][q][r]};
+                }
+        __syncthreads();
+        gemm_lds_acc<T>(xs, enc_ptr<T2>(bases, pr.b), re, im);
+        __syncthreads();  // xs is rewritten below
+    }
     T2 *C = enc_ptr<T2>(bases, tk.c);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -785,13 +877,14 @@ size_t bk_lds_bytes(int n, int nthr, bool lds) {
 #define BK64_NW 8  // 8 waves: 8 elements of A and of Z per thread
 #endif
 template <typename T>
-hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &b, const DArrays &D, int *status,
+hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const GemmPair *pairs, const Bases &b,
+                     const DArrays &D, int *status,
                      double2 *scratch, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
     if (maxn <= 64) {
         hipLaunchKernelGGL((bk64_kernel<T2, BK64_NW>), dim3((unsigned)ntask), dim3(64 * BK64_NW), 0, s,
-                           tasks, b, D, status);
+                           tasks, pairs, b, D, status);
         return hipGetLastError();
     }
     int nthr = ((maxn + 63) / 64) * 64;
@@ -851,7 +944,8 @@ hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipSt
 #define D3M_INST(T)                                                                                          \
     template hipError_t launch_fill_zero<T>(void *, int64_t, hipStream_t);                                     \
     template hipError_t launch_coo_scatter<T>(void *, const int64_t *, const double2 *, int64_t, hipStream_t); \
-    template hipError_t launch_bk<T>(const BkTask *, int64_t, int, const Bases &, const DArrays &, int *,      \
+    template hipError_t launch_bk<T>(const BkTask *, int64_t, int, const GemmPair *, const Bases &,            \
+                                     const DArrays &, int *,                                                  \
                                      double2 *, hipStream_t);                                                 \
     template hipError_t launch_gemm<T>(const GemmTask *, int64_t, const GemmPair *, const Bases &, int,        \
                                        hipStream_t);                                                          \

@@ -25,7 +25,8 @@ hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_coo_scatter(void *M, const int64_t *off, const double2 *val, int64_t n, hipStream_t s);
 template <typename T>
-hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const Bases &b, const DArrays &D, int *status,
+hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const GemmPair *pairs, const Bases &b,
+                     const DArrays &D, int *status,
                      double2 *scratch, hipStream_t s);
 size_t bk_lds_bytes(int n, int nthr, bool lds);
 template <typename T>

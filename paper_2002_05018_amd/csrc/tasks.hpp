@@ -47,6 +47,8 @@ struct BkTask {
     int32_t n;     // block order
     int32_t ldt;   // element stride between column tiles of the block
     int32_t status;
+    int32_t np;    // pending updates A -= X W^T applied to the block first:
+    int32_t p0;    //   pairs (X, W) p0 .. p0 + np - 1 of the pair list (one-tile blocks)
     int32_t pad;
 };
 
@@ -56,7 +58,9 @@ struct ScaleTask {
     int64_t x, w;          // X tile, output tile
     int64_t xprev, xnext;  // neighbouring X tiles in the same tile row (-1: none)
     int64_t drow;          // D-array row of column 0 of this tile
-    int32_t ncols, pad;
+    int32_t ncols;
+    int32_t nq;            // pending updates of the panel's input tile (fused panel only):
+    int32_t q0, pad;       //   pairs (X, W) q0 .. q0 + nq - 1, applied before the product
 };
 
 // Assembly of one tile of the LM Schur complement from <= 2 subdomains
