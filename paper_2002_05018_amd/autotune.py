@@ -47,7 +47,11 @@ def signature(solver, nrhs, precision) -> str:
     """Key of a tuning result: problem shape, right-hand sides, precision and device."""
     import torch
     i = solver.info
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    if torch.cuda.is_available():  # architecture and compute units (the marketing name varies by runtime)
+        prop = torch.cuda.get_device_properties(0)
+        dev = f"{prop.gcnArchName.split(':')[0]}/{prop.multi_processor_count}"
+    else:
+        dev = "none"
     return json.dumps({"n_edges": i["n_edges"], "n_subdomains": i["n_subdomains"], "n_blocks": i["n_blocks"],
                        "n_lm": i["n_lm"], "n_problems": i["n_problems"], "nrhs": int(nrhs),
                        "precision": _PREC.get(precision, str(precision)), "device": dev}, sort_keys=True)
