@@ -3,6 +3,7 @@
 // block, reference [bunch1977] of the paper), the complex Schur-update GEMM on
 // MFMA, the L-hat = X D^{-1} scaling and the assembly of -K.
 #include <climits>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -586,11 +587,62 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, cons
 }
 
 // ------------------------------------------------- complex GEMM (MFMA) --
-// C (=|-=) sum_p A_p B_p^T for 64x64 complex tiles, 4M (four real MFMAs per
-// complex product), 256 threads: wave w owns the 32x32 quadrant
+// C (=|-=) sum_p A_p B_p^T for 64x64 complex tiles on real MFMAs (three per
+// complex product in FP64, four in FP32), 256 threads: wave w owns the 32x32 quadrant
 // (rows 32*(w>>1), cols 32*(w&1)).  The MFMA's first operand is taken from B
 // and its second from A so that the accumulator holds C^T, whose per-lane
 // layout maps to contiguous runs of column-major C.
+
+// One k-step (4 inner indices) of the complex products of a wave's 2x2
+// sub-tiles.  FP64 uses three real products per complex one (P1 = Re w Re x,
+// P2 = Im w Im x, P3 = (Re w + Im w)(Re x + Im x); Re = P1 - P2,
+// Im = P3 - P1 - P2, combined by cmma_finish): a quarter fewer MFMAs than the
+// four-product form, whose rounding (cancellation in Im when it is small next
+// to the operands) stays at the FP64 rounding level.  FP32 keeps the four
+// products (re, im accumulate directly; p3 is unused), so that the factors the
+// refinement starts from carry no extra error.
+template <typename T>
+__device__ __forceinline__ void cmma_step(const typename C2T<T>::type (&wq)[2], const typename C2T<T>::type (&xm)[2],
+                                          typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2],
+                                          typename Mfma<T>::acc (&p3)[2][2]) {
+    using M = Mfma<T>;
+    if constexpr (std::is_same<T, double>::value) {
+        const T ws[2] = {wq[0].x + wq[0].y, wq[1].x + wq[1].y};
+        const T xsum[2] = {xm[0].x + xm[0].y, xm[1].x + xm[1].y};
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
+                im[m][q] = M::mma(wq[q].y, xm[m].y, im[m][q]);
+                p3[m][q] = M::mma(ws[q], xsum[m], p3[m][q]);
+            }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
+                re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
+                im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
+                im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
+            }
+    }
+}
+template <typename T>
+__device__ __forceinline__ void cmma_finish(typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2],
+                                            const typename Mfma<T>::acc (&p3)[2][2]) {
+    if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const typename Mfma<T>::acc r = re[m][q] - im[m][q];
+                im[m][q] = p3[m][q] - re[m][q] - im[m][q];
+                re[m][q] = r;
+            }
+    }
+}
 
 // Accumulates sum_p A_p B_p^T of one task into the per-wave quadrant
 // accumulators (C^T layout, see above).
@@ -603,8 +655,9 @@ __device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    acc_t p3[2][2];
     for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 2; ++q) { re[m][q] = acc_t{0, 0, 0, 0}; im[m][q] = acc_t{0, 0, 0, 0}; }
+        for (int q = 0; q < 2; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
     // operands of k-step s + 2 are loaded while k-step s runs
     constexpr int PF = 2;
     for (int p = 0; p < tk.np; ++p) {
@@ -631,17 +684,10 @@ __device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair
                 x[s][0] = A[kcol + wr + li];
                 x[s][1] = A[kcol + wr + 16 + li];
             }
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
-                    re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
-                    im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
-                    im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
-                }
+            cmma_step<T>(wq, xm, re, im, p3);
         }
     }
+    cmma_finish<T>(re, im, p3);
 }
 
 // One product A B^T with A staged in LDS (column-major, column stride 65),
@@ -655,27 +701,23 @@ __device__ __forceinline__ void gemm_lds_acc(const typename C2T<T>::type *alds, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    acc_t p3[2][2];
     for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 2; ++q) { re[m][q] = acc_t{0, 0, 0, 0}; im[m][q] = acc_t{0, 0, 0, 0}; }
+        for (int q = 0; q < 2; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < 64; k0 += 4) {
         const int k = k0 + lk;
         const T2 wq[2] = {B[k * 64 + wc + li], B[k * 64 + wc + 16 + li]};
         const T2 xm[2] = {alds[k * 65 + wr + li], alds[k * 65 + wr + 16 + li]};
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
-                re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
-                im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
-                im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
-            }
+        cmma_step<T>(wq, xm, re, im, p3);
     }
+    cmma_finish<T>(re, im, p3);
 }
 
+// Three work-groups per compute unit: room for the three FP64 accumulator sets
+// of a quadrant without spills.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
+__global__ __launch_bounds__(256, 3) void gemm_nt_kernel(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs,
                                                       Bases bases) {
     using T2 = typename C2T<T>::type;
     using M = Mfma<T>;
@@ -688,8 +730,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
     const int li = lane & 15, lk = lane >> 4;
     T2 *C = enc_ptr<T2>(bases, tk.c);
     // the target tile of an update is loaded first, so its latency overlaps the products
+    // (FP64 keeps its three accumulator sets in registers instead and reads the
+    // target after the products)
+    constexpr bool kPreC = MODE == 1 && !std::is_same<T, double>::value;
     T2 cpre[2][2][4];
-    if (MODE == 1) {
+    if (kPreC) {
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -708,8 +753,12 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
                 const int row = wr + 16 * m + li;
                 const int col = wc + 16 * q + M::out_row(lk, r);
                 T2 *c = C + col * 64 + row;
-                if (MODE == 0) *c = T2{re[m][q][r], im[m][q][r]};
-                else *c = T2{cpre[m][q][r].x - re[m][q][r], cpre[m][q][r].y - im[m][q][r]};
+                if (MODE == 0) {
+                    *c = T2{re[m][q][r], im[m][q][r]};
+                } else {
+                    const T2 old = kPreC ? cpre[m][q][r] : *c;
+                    *c = T2{old.x - re[m][q][r], old.y - im[m][q][r]};
+                }
             }
 }
 
@@ -717,8 +766,10 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmTask *tasks, int
 // L-hat = X D^{-1} over the tile's own columns (1x1 and 2x2 pivots of a
 // block of one tile never reach a neighbouring tile).  Task i of the panel
 // list and task i of the scale list describe the same tile.
+// (its LDS tile allows two work-groups per compute unit; the bound lets the
+// FP64 accumulators of the three-product form stay in registers)
 template <typename T>
-__global__ __launch_bounds__(256) void panel_scale_kernel(const GemmTask *tasks, const ScaleTask *stasks,
+__global__ __launch_bounds__(256, 2) void panel_scale_kernel(const GemmTask *tasks, const ScaleTask *stasks,
                                                           int64_t ntask, const GemmPair *pairs, Bases bases,
                                                           DArrays D) {
     using T2 = typename C2T<T>::type;
