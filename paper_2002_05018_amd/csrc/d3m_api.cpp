@@ -675,10 +675,15 @@ int residual_inf(d3m_problem *h, const double2 *f, const double2 *E, int nrhs, s
     return fetch_norms(h, (int)n, out, s);
 }
 
-// max over problems and right-hand sides of ||r||_inf / ||f||_inf
+// max over problems and right-hand sides of ||r||_inf / ||f||_inf (NaN if any
+// norm is NaN, so that a non-finite solution never counts as converged)
 double relative_residual(const std::vector<double> &rn, const std::vector<double> &fn) {
     double res = 0.0;
-    for (size_t i = 0; i < rn.size(); ++i) res = std::max(res, fn[i] > 0 ? rn[i] / fn[i] : rn[i]);
+    for (size_t i = 0; i < rn.size(); ++i) {
+        const double q = fn[i] > 0 ? rn[i] / fn[i] : rn[i];
+        if (q != q) return q;
+        res = std::max(res, q);
+    }
     return res;
 }
 
@@ -695,7 +700,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
             if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
             const double res = relative_residual(rn, fn);
             info->iterations = 0;
-            info->converged = 1;
+            info->converged = res == res ? 1 : 0;  // a NaN residual passes no test
             info->residual = res;
             info->copy_discrepancy = 0.0;
         }

@@ -2,6 +2,7 @@
 // refinement / adjoint helpers.  Vector tiles hold 64 rows x nrhs columns,
 // column-major (one right-hand side after another), so one 64 x 64 factor
 // tile is applied to many right-hand sides per read.
+#include <climits>
 #include <type_traits>
 
 #include "common.hpp"
@@ -440,43 +441,97 @@ __global__ void vcollect_kernel(double2 *E, const T2 *X, const int64_t *cmap, in
     E[idx] = ACC ? cadd(E[idx], v) : v;
 }
 
-// Folds v >= 0 of a lane into nmax[g] (per-lane group g, nmax holds bit
-// patterns of non-negative doubles, monotone under unsigned comparison).  A
-// wave whose lanes share one group reduces first and issues one atomic.
-__device__ __forceinline__ void fold_max(unsigned long long *nmax, int64_t g, double v, bool live) {
-    const int64_t g0 = __shfl(g, 0), g63 = __shfl(g, 63);
-    if (g0 == g63) {
-        for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-        if ((threadIdx.x & 63) == 0 && g0 >= 0) atomicMax(&nmax[g0], (unsigned long long)__double_as_longlong(v));
-    } else if (live && g >= 0) {
-        atomicMax(&nmax[g], (unsigned long long)__double_as_longlong(v));
+// Norm reductions.  nmax[p * nrhs + c] holds the bit pattern of a
+// non-negative double (monotone under unsigned comparison) or of a NaN, which
+// compares above every number, so a NaN anywhere in the data reaches the host.
+// A block covers kRowsPer * 256 consecutive rows; each thread keeps running
+// maxima for its rows and the block combines them in LDS, so a block that
+// lies inside one problem issues one atomic per right-hand side.
+constexpr int kRowsPer = 8;
+
+__device__ __forceinline__ double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
+
+__device__ __forceinline__ void atomic_max_bits(unsigned long long *a, double v) {
+    atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// Combines the running maxima m[c] (c < nc) of every thread of the block, for
+// problem pcur (-1: the thread saw no row), into nmax[pcur * nrhs + c0 + c].
+// Called by every thread of the block.
+template <int NC>
+__device__ __forceinline__ void block_fold_max(unsigned long long *nmax, int pcur, const double (&m)[NC], int nrhs,
+                                               int c0, int nc) {
+    __shared__ int s_pmin, s_pmax;
+    __shared__ double s_red[NC][4];
+    if (threadIdx.x == 0) {
+        s_pmin = INT_MAX;
+        s_pmax = -1;
+    }
+    __syncthreads();
+    if (pcur >= 0) {
+        atomicMin(&s_pmin, pcur);
+        atomicMax(&s_pmax, pcur);
+    }
+    __syncthreads();
+    const int pmin = s_pmin, pmax = s_pmax;
+    if (pmax < 0) return;  // the whole block is past the last row
+    if (pmin == pmax) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double v = m[c];
+            for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+            if (lane == 0) s_red[c][wv] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nc) {
+            const int c = threadIdx.x;
+            const double v = nanmax(nanmax(s_red[c][0], s_red[c][1]), nanmax(s_red[c][2], s_red[c][3]));
+            atomic_max_bits(&nmax[(int64_t)pmin * nrhs + c0 + c], v);
+        }
+    } else if (pcur >= 0) {  // a block across a problem boundary (batches)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < nc) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c0 + c], m[c]);
     }
 }
 
-// r = f - S E (CSR of the global FEM matrix, FP64).  One thread per row and
-// RES_COLS right-hand sides (blockIdx.y selects them): the row's entries are
-// read once for all of them, and the gathers of E for one entry are
-// independent of each other.  nmax[p * nrhs + c] (zeroed by the caller) gets
-// the largest |r[c][e]| (modulus) over the rows e of problem p = eprob[e].
+// r = f - S E (CSR of the global FEM matrix, FP64).  RES_COLS right-hand sides
+// per block column (blockIdx.y); a thread takes kRowsPer rows 256 apart, and a
+// row's entries are read once for all of its right-hand sides, whose gathers
+// of E are independent of each other.  nmax[p * nrhs + c] (zeroed by the
+// caller) gets the largest |r[c][e]| (modulus) over the rows e of problem
+// p = eprob[e].
 constexpr int RES_COLS = 16;
 
 __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *E,
                                                        const int64_t *rowptr, const int32_t *col, const double2 *val,
                                                        const int32_t *eprob, int64_t ne, int nrhs,
                                                        unsigned long long *nmax) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c0 = blockIdx.y * RES_COLS;
     const int nc = min(RES_COLS, nrhs - c0);
-    const bool live = row < ne;
-    double2 s[RES_COLS];
+    const int64_t base = (int64_t)blockIdx.x * 256 * kRowsPer;
+    int pcur = -1;
+    double m[RES_COLS];
 #pragma unroll
-    for (int c = 0; c < RES_COLS; ++c) s[c] = make_double2(0, 0);
-    int64_t pbase = -1;
-    if (live) {
-        pbase = (int64_t)eprob[row] * nrhs + c0;
+    for (int c = 0; c < RES_COLS; ++c) m[c] = 0.0;
+    for (int i = 0; i < kRowsPer; ++i) {
+        const int64_t row = base + threadIdx.x + 256 * i;
+        if (row >= ne) break;
+        const int p = eprob[row];
+        if (p != pcur) {  // a new problem (batches): fold this thread's maxima so far
+            if (pcur >= 0) {
 #pragma unroll
-        for (int c = 0; c < RES_COLS; ++c)
-            if (c < nc) s[c] = f[(int64_t)(c0 + c) * ne + row];
+                for (int c = 0; c < RES_COLS; ++c)
+                    if (c < nc) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c0 + c], m[c]);
+            }
+            pcur = p;
+#pragma unroll
+            for (int c = 0; c < RES_COLS; ++c) m[c] = 0.0;
+        }
+        double2 s[RES_COLS];
+#pragma unroll
+        for (int c = 0; c < RES_COLS; ++c) s[c] = c < nc ? f[(int64_t)(c0 + c) * ne + row] : make_double2(0, 0);
         const int64_t k1 = rowptr[row + 1];
         for (int64_t k = rowptr[row]; k < k1; ++k) {
             const double2 v = val[k];
@@ -487,28 +542,35 @@ __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2
         }
 #pragma unroll
         for (int c = 0; c < RES_COLS; ++c)
-            if (c < nc) r[(int64_t)(c0 + c) * ne + row] = s[c];
+            if (c < nc) {
+                r[(int64_t)(c0 + c) * ne + row] = s[c];
+                m[c] = nanmax(m[c], sqrt(s[c].x * s[c].x + s[c].y * s[c].y));
+            }
     }
-#pragma unroll
-    for (int c = 0; c < RES_COLS; ++c)
-        if (c < nc) fold_max(nmax, live ? pbase + c : -1, sqrt(s[c].x * s[c].x + s[c].y * s[c].y), live);
+    block_fold_max<RES_COLS>(nmax, pcur, m, nrhs, c0, nc);
 }
 
 // nmax[p * nrhs + c] = max |v[c][e]| over the rows e of problem p (|z| =
-// modulus); one thread per element, blockIdx.y = right-hand side
-__global__ void rownorm_max_kernel(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne,
-                                   int nrhs) {
+// modulus); blockIdx.y = right-hand side, kRowsPer elements per thread
+__global__ __launch_bounds__(256) void rownorm_max_kernel(unsigned long long *nmax, const double2 *v,
+                                                          const int32_t *eprob, int64_t ne, int nrhs) {
     const int c = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = e < ne;
-    double m = 0.0;
-    int64_t g = -1;
-    if (live) {
+    const int64_t base = (int64_t)blockIdx.x * 256 * kRowsPer;
+    int pcur = -1;
+    double m[1] = {0.0};
+    for (int i = 0; i < kRowsPer; ++i) {
+        const int64_t e = base + threadIdx.x + 256 * i;
+        if (e >= ne) break;
+        const int p = eprob[e];
+        if (p != pcur) {
+            if (pcur >= 0) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c], m[0]);
+            pcur = p;
+            m[0] = 0.0;
+        }
         const double2 z = v[(int64_t)c * ne + e];
-        m = sqrt(z.x * z.x + z.y * z.y);
-        g = (int64_t)eprob[e] * nrhs + c;
+        m[0] = nanmax(m[0], sqrt(z.x * z.x + z.y * z.y));
     }
-    fold_max(nmax, g, m, live);
+    block_fold_max<1>(nmax, pcur, m, nrhs, c, 1);
 }
 
 __global__ void conj_kernel(double2 *out, const double2 *in, int64_t n) {
@@ -631,13 +693,14 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
 hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
                            const double2 *val, const int32_t *eprob, int64_t ne, int nrhs, unsigned long long *nmax,
                            hipStream_t s) {
-    dim3 grid(g1(ne).x, (unsigned)((nrhs + RES_COLS - 1) / RES_COLS));
+    dim3 grid(g1(ne, 256 * kRowsPer).x, (unsigned)((nrhs + RES_COLS - 1) / RES_COLS));
     hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, r, f, E, rowptr, col, val, eprob, ne, nrhs, nmax);
     return hipGetLastError();
 }
 hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne, int nrhs,
                               hipStream_t s) {
-    hipLaunchKernelGGL(rownorm_max_kernel, dim3(g1(ne).x, (unsigned)nrhs), dim3(256), 0, s, nmax, v, eprob, ne, nrhs);
+    hipLaunchKernelGGL(rownorm_max_kernel, dim3(g1(ne, 256 * kRowsPer).x, (unsigned)nrhs), dim3(256), 0, s, nmax, v,
+                       eprob, ne, nrhs);
     return hipGetLastError();
 }
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s) {

@@ -138,3 +138,48 @@ def test_autotune_picks_a_valid_tuning():
     assert s.tuning() == res["tuning"]
     s.factor("fp64")
     assert _rel(s.solve(f).cpu().numpy(), want) <= 1e-12
+
+
+def test_batch_residual_is_per_problem():
+    """The reported residual is the largest over problems and right-hand sides
+    of ||f_p - S_p E_p||_inf / ||f_p||_inf.  Problem p's load is scaled by
+    1e3^p, which leaves each problem's relative residual unchanged, so the
+    figure must match the host recomputation from the returned field (to the
+    rounding of r, a few per cent of a residual near 1e-13), while a norm
+    taken across problems would be off by orders of magnitude.  The small
+    problems put problem boundaries inside the reduction's row blocks."""
+    from oracle.d3m import relative_residual
+    from oracle.fem import GlobalFEM
+    probs, s, f, eo, ref = _batch()
+    fs = f.copy()
+    for p in range(len(probs)):
+        fs[:, eo[p]:eo[p + 1]] *= 1e3 ** p
+    s.factor("fp64")
+    E, info = s.solve(torch.from_numpy(fs).cuda(), with_info=True)
+    E = E.cpu().numpy()
+    want = 0.0
+    for p, prob in enumerate(probs):
+        S = GlobalFEM(prob.xyz, prob.tets, prob.eps_r, prob.k).S
+        sl = slice(eo[p], eo[p + 1])
+        want = max(want, relative_residual(S, E[:, sl], fs[:, sl]))
+    assert info["converged"]
+    assert abs(info["residual"] - want) <= 0.05 * want, (info["residual"], want)
+
+
+def test_nonfinite_load_never_counts_as_converged():
+    """A NaN in the load makes the field NaN; the residual reduction must pass
+    the NaN on (FP64: residual NaN, not converged; FP32 factors: refinement
+    reports no convergence) instead of dropping it as a maximum would."""
+    from paper_2002_05018_amd import Solver
+    from paper_2002_05018_amd._lib import D3MError
+    prob = W.make_problem(4, (2, 1, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=3, seed=24)
+    s = Solver.from_problem(prob)
+    f = s.rhs_planewave(prob.dirs, prob.pols)
+    f[1, 7] = np.nan
+    fd = torch.from_numpy(f).cuda()
+    s.factor("fp64")
+    _, info = s.solve(fd, with_info=True)
+    assert np.isnan(info["residual"]) and not info["converged"]
+    s.factor("fp32_ir")
+    with pytest.raises(D3MError):
+        s.solve(fd, with_info=True)
