@@ -264,7 +264,11 @@ typedef struct {
                                 K are applied by that level's pivot and panel
                                 launches (one launch fewer per level) instead
                                 of a separate update launch; default 0       */
-    int32_t reserved[2];
+    int32_t panel_rows;      /* rows of a panel tile per work-group: 64
+                                (default) or 16 (four work-groups per tile,
+                                so a short block column's panel products
+                                run on four times as many compute units)    */
+    int32_t reserved[1];
 } d3m_tuning;
 
 /* Read / replace the tuning.  A new s1_block, k_block or k_fuse rebuilds the factor schedule

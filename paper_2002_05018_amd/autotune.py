@@ -15,6 +15,8 @@ launch shapes the schedules expose:
   after its critical updates;
 * ``k_fuse``: whether the updates of the next level's columns of K get their
   own launch or are applied inside that level's pivot and panel launches;
+* ``panel_rows``: rows of a panel tile per work-group (64, or 16 with four
+  work-groups per tile);
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
   (16 or 32 columns of the MFMA tile).
 
@@ -36,11 +38,12 @@ DEFAULT_SPACE = {
     "lookahead_tasks": (512, 128, 2048),
     "side_early": (0, 1),
     "k_fuse": (0, 1),
+    "panel_rows": (64, 16),
     "solve_cols": (32, 16),
 }
 _PREC = {0: "fp64", 1: "fp32_ir", "fp64": "fp64", "fp32_ir": "fp32_ir"}
 # parameters that change the factorisation schedule (the rest only the solve)
-_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early", "k_fuse")
+_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early", "k_fuse", "panel_rows")
 
 
 def signature(solver, nrhs, precision) -> str:

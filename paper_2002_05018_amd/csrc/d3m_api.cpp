@@ -430,7 +430,7 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
             h->prof_begin(KID_PANEL, ev, s);
             if (st.fused_scale) {
                 HIPCHK(launch_panel_scale<T>(h->d_gemm + st.pan0, h->d_scale + st.sc0, st.npan, h->d_pairs, b, h->D,
-                                             s));
+                                             h->tune.panel_rows == 16 ? 16 : 64, s));
             } else {
                 HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
                 HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
@@ -840,6 +840,8 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     if (t->k_block < 0 || t->k_block > 16) return fail(D3M_EINVAL, "k_block must be in [0, 16]");
     if (t->side_early != 0 && t->side_early != 1) return fail(D3M_EINVAL, "side_early must be 0 or 1");
     if (t->k_fuse != 0 && t->k_fuse != 1) return fail(D3M_EINVAL, "k_fuse must be 0 or 1");
+    if (t->panel_rows != 0 && t->panel_rows != 16 && t->panel_rows != 64)
+        return fail(D3M_EINVAL, "panel_rows must be 0, 16 or 64");
     const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block, old_f = h->tune.k_fuse;
     h->drop_graphs();
     h->tune = *t;

@@ -332,10 +332,12 @@ struct BkHead {
     int pad;
 };
 
-// sum_p A_p B_p^T of one task on 4 waves (defined with the GEMM kernels)
-template <typename T>
-__device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases,
-                                              typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]);
+// sum_p A_p B_p^T of one task for a wave's MS x QS sub-tiles of 16 x 16 at
+// rows wr, columns wc (defined with the GEMM kernels)
+template <typename T, int MS, int QS>
+__device__ __forceinline__ void gemm_sub_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases, int wr,
+                                             int wc, typename Mfma<T>::acc (&re)[MS][QS],
+                                             typename Mfma<T>::acc (&im)[MS][QS]);
 
 template <typename T2, int NW>
 __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, const GemmPair *pairs, Bases bases,
@@ -371,26 +373,24 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, cons
     }
     if (tk.np > 0) {
         // pending updates of the block, A -= sum_p X_p W_p^T (the previous
-        // step's updates of this column): the first four waves form U on
-        // MFMA (the update GEMM's tile product), U goes through LDS, and every
+        // step's updates of this column): the eight waves form U on MFMA
+        // (the update GEMM's tile product), U goes through LDS, and every
         // thread takes U(i, s) for i >= s and U(s, i) above the diagonal, so
         // that both triangles carry the lower one's rounding (U is symmetric:
         // W = X D^{-1})
         using T = typename T2S<T2>::type;
         using M = Mfma<T>;
-        if (t < 256) {
-            typename M::acc ure[2][2], uim[2][2];
+        {
+            // wave w forms the 32 x 16 block at rows 32 (w / 4), columns 16 (w % 4)
+            typename M::acc ure[2][1], uim[2][1];
             const GemmTask ut{0, tk.p0, tk.np};
-            gemm_task_acc<T>(ut, pairs, bases, ure, uim);
-            const int wr = (w >> 1) * 32, wc = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+            const int wr = (w >> 2) * 32, wc = (w & 3) * 16, li = lane & 15, lk = lane >> 4;
+            gemm_sub_acc<T, 2, 1>(ut, pairs, bases, wr, wc, ure, uim);
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        stage[(wc + 16 * q + M::out_row(lk, r)) * SLD + wr + 16 * m + li] =
-                            make_double2(ure[m][q][r], uim[m][q][r]);
+                for (int r = 0; r < 4; ++r)
+                    stage[(wc + M::out_row(lk, r)) * SLD + wr + 16 * m + li] = make_double2(ure[m][0][r], uim[m][0][r]);
         }
         __syncthreads();
 #pragma unroll
@@ -593,35 +593,38 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, cons
 // and its second from A so that the accumulator holds C^T, whose per-lane
 // layout maps to contiguous runs of column-major C.
 
-// One k-step (4 inner indices) of the complex products of a wave's 2x2
-// sub-tiles.  FP64 uses three real products per complex one (P1 = Re w Re x,
-// P2 = Im w Im x, P3 = (Re w + Im w)(Re x + Im x); Re = P1 - P2,
-// Im = P3 - P1 - P2, combined by cmma_finish): a quarter fewer MFMAs than the
-// four-product form, whose rounding (cancellation in Im when it is small next
-// to the operands) stays at the FP64 rounding level.  FP32 keeps the four
-// products (re, im accumulate directly; p3 is unused), so that the factors the
-// refinement starts from carry no extra error.
-template <typename T>
-__device__ __forceinline__ void cmma_step(const typename C2T<T>::type (&wq)[2], const typename C2T<T>::type (&xm)[2],
-                                          typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2],
-                                          typename Mfma<T>::acc (&p3)[2][2]) {
+// One k-step (4 inner indices) of the complex products of a wave's MS x QS
+// sub-tiles of 16 x 16.  FP64 uses three real products per complex one
+// (P1 = Re w Re x, P2 = Im w Im x, P3 = (Re w + Im w)(Re x + Im x);
+// Re = P1 - P2, Im = P3 - P1 - P2, combined by cmma_finish): a quarter fewer
+// MFMAs than the four-product form, whose rounding (cancellation in Im when it
+// is small next to the operands) stays at the FP64 rounding level.  FP32
+// keeps the four products (re, im accumulate directly; p3 is unused), so that
+// the factors the refinement starts from carry no extra error.
+template <typename T, int MS, int QS>
+__device__ __forceinline__ void cmma_step(const typename C2T<T>::type (&wq)[QS], const typename C2T<T>::type (&xm)[MS],
+                                          typename Mfma<T>::acc (&re)[MS][QS], typename Mfma<T>::acc (&im)[MS][QS],
+                                          typename Mfma<T>::acc (&p3)[MS][QS]) {
     using M = Mfma<T>;
     if constexpr (std::is_same<T, double>::value) {
-        const T ws[2] = {wq[0].x + wq[0].y, wq[1].x + wq[1].y};
-        const T xsum[2] = {xm[0].x + xm[0].y, xm[1].x + xm[1].y};
+        T ws[QS], xsum[MS];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < QS; ++q) ws[q] = wq[q].x + wq[q].y;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+        for (int m = 0; m < MS; ++m) xsum[m] = xm[m].x + xm[m].y;
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
                 re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
                 im[m][q] = M::mma(wq[q].y, xm[m].y, im[m][q]);
                 p3[m][q] = M::mma(ws[q], xsum[m], p3[m][q]);
             }
     } else {
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < MS; ++m)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < QS; ++q) {
                 re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
                 re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
                 im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
@@ -629,14 +632,14 @@ __device__ __forceinline__ void cmma_step(const typename C2T<T>::type (&wq)[2], 
             }
     }
 }
-template <typename T>
-__device__ __forceinline__ void cmma_finish(typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2],
-                                            const typename Mfma<T>::acc (&p3)[2][2]) {
+template <typename T, int MS, int QS>
+__device__ __forceinline__ void cmma_finish(typename Mfma<T>::acc (&re)[MS][QS], typename Mfma<T>::acc (&im)[MS][QS],
+                                            const typename Mfma<T>::acc (&p3)[MS][QS]) {
     if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < MS; ++m)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < QS; ++q) {
                 const typename Mfma<T>::acc r = re[m][q] - im[m][q];
                 im[m][q] = p3[m][q] - re[m][q] - im[m][q];
                 re[m][q] = r;
@@ -644,74 +647,94 @@ __device__ __forceinline__ void cmma_finish(typename Mfma<T>::acc (&re)[2][2], t
     }
 }
 
-// Accumulates sum_p A_p B_p^T of one task into the per-wave quadrant
-// accumulators (C^T layout, see above).
-template <typename T>
-__device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases,
-                                              typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]) {
+// Accumulates sum_p A_p B_p^T of one task for the output rows wr + 16 m + i
+// (m < MS) and columns wc + 16 q + i (q < QS), i < 16, of the calling wave
+// (C^T layout, see above).
+template <typename T, int MS, int QS>
+__device__ __forceinline__ void gemm_sub_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases, int wr,
+                                             int wc, typename Mfma<T>::acc (&re)[MS][QS],
+                                             typename Mfma<T>::acc (&im)[MS][QS]) {
     using T2 = typename C2T<T>::type;
-    using M = Mfma<T>;
-    using acc_t = typename M::acc;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    using acc_t = typename Mfma<T>::acc;
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    acc_t p3[2][2];
-    for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 2; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
+    acc_t p3[MS][QS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m)
+#pragma unroll
+        for (int q = 0; q < QS; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
     // operands of k-step s + 2 are loaded while k-step s runs
     constexpr int PF = 2;
     for (int p = 0; p < tk.np; ++p) {
         const GemmPair pr = pairs[tk.p0 + p];
         const T2 *A = enc_ptr<T2>(bases, pr.a);
         const T2 *B = enc_ptr<T2>(bases, pr.b);
-        T2 w[PF][2], x[PF][2];
+        T2 w[PF][QS], x[PF][MS];
 #pragma unroll
         for (int s = 0; s < PF; ++s) {
             const int kcol = (4 * s + lk) * 64;
-            w[s][0] = B[kcol + wc + li];
-            w[s][1] = B[kcol + wc + 16 + li];
-            x[s][0] = A[kcol + wr + li];
-            x[s][1] = A[kcol + wr + 16 + li];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) w[s][q] = B[kcol + wc + 16 * q + li];
+#pragma unroll
+            for (int m = 0; m < MS; ++m) x[s][m] = A[kcol + wr + 16 * m + li];
         }
 #pragma unroll
         for (int k0 = 0; k0 < 64; k0 += 4) {
             const int s = (k0 / 4) % PF;
-            const T2 wq[2] = {w[s][0], w[s][1]}, xm[2] = {x[s][0], x[s][1]};
+            T2 wq[QS], xm[MS];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) wq[q] = w[s][q];
+#pragma unroll
+            for (int m = 0; m < MS; ++m) xm[m] = x[s][m];
             if (k0 + 4 * PF < 64) {
                 const int kcol = (k0 + 4 * PF + lk) * 64;
-                w[s][0] = B[kcol + wc + li];
-                w[s][1] = B[kcol + wc + 16 + li];
-                x[s][0] = A[kcol + wr + li];
-                x[s][1] = A[kcol + wr + 16 + li];
+#pragma unroll
+                for (int q = 0; q < QS; ++q) w[s][q] = B[kcol + wc + 16 * q + li];
+#pragma unroll
+                for (int m = 0; m < MS; ++m) x[s][m] = A[kcol + wr + 16 * m + li];
             }
-            cmma_step<T>(wq, xm, re, im, p3);
+            cmma_step<T, MS, QS>(wq, xm, re, im, p3);
         }
     }
-    cmma_finish<T>(re, im, p3);
+    cmma_finish<T, MS, QS>(re, im, p3);
 }
 
-// One product A B^T with A staged in LDS (column-major, column stride 65),
-// B from memory; same operand mapping and accumulator layout as gemm_task_acc.
+// The same for the wave's 32x32 quadrant of a 256-thread work-group: wave w
+// owns rows 32 (w >> 1) and columns 32 (w & 1) onwards.
 template <typename T>
-__device__ __forceinline__ void gemm_lds_acc(const typename C2T<T>::type *alds, const typename C2T<T>::type *B,
-                                             typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]) {
+__device__ __forceinline__ void gemm_task_acc(const GemmTask &tk, const GemmPair *pairs, const Bases &bases,
+                                              typename Mfma<T>::acc (&re)[2][2], typename Mfma<T>::acc (&im)[2][2]) {
+    const int wave = (threadIdx.x >> 6) & 3;
+    gemm_sub_acc<T, 2, 2>(tk, pairs, bases, (wave >> 1) * 32, (wave & 1) * 32, re, im);
+}
+
+// One product A B^T with A staged in LDS (column-major, column stride lda,
+// rows wr + 16 m + i of the calling wave), B from memory; same operand
+// mapping and accumulator layout as gemm_sub_acc.
+template <typename T, int MS, int QS>
+__device__ __forceinline__ void gemm_lds_sub(const typename C2T<T>::type *alds, int lda,
+                                             const typename C2T<T>::type *B, int wr, int wc,
+                                             typename Mfma<T>::acc (&re)[MS][QS], typename Mfma<T>::acc (&im)[MS][QS]) {
     using T2 = typename C2T<T>::type;
-    using M = Mfma<T>;
-    using acc_t = typename M::acc;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    using acc_t = typename Mfma<T>::acc;
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    acc_t p3[2][2];
-    for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 2; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
+    acc_t p3[MS][QS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m)
+#pragma unroll
+        for (int q = 0; q < QS; ++q) re[m][q] = im[m][q] = p3[m][q] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < 64; k0 += 4) {
         const int k = k0 + lk;
-        const T2 wq[2] = {B[k * 64 + wc + li], B[k * 64 + wc + 16 + li]};
-        const T2 xm[2] = {alds[k * 65 + wr + li], alds[k * 65 + wr + 16 + li]};
-        cmma_step<T>(wq, xm, re, im, p3);
+        T2 wq[QS], xm[MS];
+#pragma unroll
+        for (int q = 0; q < QS; ++q) wq[q] = B[k * 64 + wc + 16 * q + li];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) xm[m] = alds[k * lda + wr + 16 * m + li];
+        cmma_step<T, MS, QS>(wq, xm, re, im, p3);
     }
-    cmma_finish<T>(re, im, p3);
+    cmma_finish<T, MS, QS>(re, im, p3);
 }
 
 // Three work-groups per compute unit: room for the three FP64 accumulator sets
@@ -805,7 +828,7 @@ __global__ __launch_bounds__(256, 2) void panel_scale_kernel(const GemmTask *tas
                     xs[col * 65 + row] = T2{a.x - re[m][q][r], a.y - im[m][q][r]};
                 }
         __syncthreads();
-        gemm_lds_acc<T>(xs, enc_ptr<T2>(bases, pr.b), re, im);
+        gemm_lds_sub<T, 2, 2>(xs, 65, enc_ptr<T2>(bases, pr.b), wr, wc, re, im);
         __syncthreads();  // xs is rewritten below
     }
     T2 *C = enc_ptr<T2>(bases, tk.c);
@@ -833,6 +856,71 @@ __global__ __launch_bounds__(256, 2) void panel_scale_kernel(const GemmTask *tas
             if (pv != 0) out = cadd(out, cmul(to_d2(xs[(c + pv) * 65 + r]), D.dinvoff[row]));
         }
         W[e] = from_d2<T2>(out);
+    }
+}
+
+// The same panel in four row strips of 16, one work-group each: the four
+// waves own 16 columns of the strip, so a tile's products are spread over
+// four compute units (the panels of a short block column are on the
+// critical path of the factorisation, one tile product per work-group
+// taking ~5 us at the MFMA peak of one compute unit).  Strips of a tile are
+// neighbours in the task order, so they run on one XCD and share W and TT
+// through its L2.
+template <typename T>
+__global__ __launch_bounds__(256) void panel_scale16_kernel(const GemmTask *tasks, const ScaleTask *stasks,
+                                                            int64_t ntask, const GemmPair *pairs, Bases bases,
+                                                            DArrays D) {
+    using T2 = typename C2T<T>::type;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    constexpr int LD = 17;
+    __shared__ T2 xs[64 * LD];  // the strip, column-major: xs[col * LD + row - wr]
+    const int64_t idx = xcd_task(4 * ntask);
+    if (idx >= 4 * ntask) return;
+    const int64_t task = idx >> 2;
+    const GemmTask tk = tasks[task];
+    const ScaleTask sk = stasks[task];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = 16 * (int)(idx & 3), wc = 16 * wave;
+    const int li = lane & 15, lk = lane >> 4;
+    acc_t re[1][1], im[1][1];
+    if (sk.nq == 0) {
+        gemm_sub_acc<T, 1, 1>(tk, pairs, bases, wr, wc, re, im);
+    } else {
+        const GemmTask ut{0, sk.q0, sk.nq};
+        gemm_sub_acc<T, 1, 1>(ut, pairs, bases, wr, wc, re, im);
+        const GemmPair pr = pairs[tk.p0];
+        const T2 *A = enc_ptr<T2>(bases, pr.a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = wc + M::out_row(lk, r);
+            const T2 a = A[col * 64 + wr + li];
+            xs[col * LD + li] = T2{a.x - re[0][0][r], a.y - im[0][0][r]};
+        }
+        __syncthreads();
+        gemm_lds_sub<T, 1, 1>(xs, LD, enc_ptr<T2>(bases, pr.b), 0, wc, re, im);
+        __syncthreads();  // xs is rewritten below
+    }
+    T2 *C = enc_ptr<T2>(bases, tk.c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = wc + M::out_row(lk, r);
+        const T2 v = T2{re[0][0][r], im[0][0][r]};
+        C[col * 64 + wr + li] = v;
+        xs[col * LD + li] = v;
+    }
+    __syncthreads();
+    T2 *W = enc_ptr<T2>(bases, sk.w);
+    for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+        const int rl = e & 15, c = e >> 4;
+        double2 out = make_double2(0, 0);
+        if (c < sk.ncols) {
+            const int64_t row = sk.drow + c;
+            const int pv = D.piv[row];
+            out = cmul(to_d2(xs[c * LD + rl]), D.dinv[row]);
+            if (pv != 0) out = cadd(out, cmul(to_d2(xs[(c + pv) * LD + rl]), D.dinvoff[row]));
+        }
+        W[c * 64 + wr + rl] = from_d2<T2>(out);
     }
 }
 
@@ -969,8 +1057,15 @@ hipError_t launch_gemm(const GemmTask *tasks, int64_t ntask, const GemmPair *pai
 
 template <typename T>
 hipError_t launch_panel_scale(const GemmTask *tasks, const ScaleTask *stasks, int64_t ntask, const GemmPair *pairs,
-                              const Bases &b, const DArrays &D, hipStream_t s) {
+                              const Bases &b, const DArrays &D, int rows, hipStream_t s) {
     if (ntask <= 0) return hipSuccess;
+    if (rows == 16) {
+        const unsigned groups = (unsigned)(((4 * ntask + kXcds - 1) / kXcds) * kXcds);
+        hipLaunchKernelGGL((panel_scale16_kernel<T>), dim3(groups), dim3(256), 0, s, tasks, stasks, ntask, pairs, b,
+                           D);
+        return hipGetLastError();
+    }
+    if (rows != 64) return hipErrorInvalidValue;
     const unsigned groups = (unsigned)(((ntask + kXcds - 1) / kXcds) * kXcds);
     hipLaunchKernelGGL((panel_scale_kernel<T>), dim3(groups), dim3(256), 0, s, tasks, stasks, ntask, pairs, b, D);
     return hipGetLastError();
@@ -1001,7 +1096,7 @@ hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipSt
     template hipError_t launch_gemm<T>(const GemmTask *, int64_t, const GemmPair *, const Bases &, int,        \
                                        hipStream_t);                                                          \
     template hipError_t launch_panel_scale<T>(const GemmTask *, const ScaleTask *, int64_t, const GemmPair *,   \
-                                              const Bases &, const DArrays &, hipStream_t);                   \
+                                              const Bases &, const DArrays &, int, hipStream_t);              \
     template hipError_t launch_scale<T>(const ScaleTask *, int64_t, const Bases &, const DArrays &,            \
                                         hipStream_t);                                                         \
     template hipError_t launch_asm<T>(const AsmTask *, int64_t, const Bases &, hipStream_t);

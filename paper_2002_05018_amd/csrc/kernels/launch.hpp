@@ -36,7 +36,7 @@ template <typename T>
 hipError_t launch_scale(const ScaleTask *tasks, int64_t ntask, const Bases &b, const DArrays &D, hipStream_t s);
 template <typename T>
 hipError_t launch_panel_scale(const GemmTask *tasks, const ScaleTask *stasks, int64_t ntask, const GemmPair *pairs,
-                              const Bases &b, const DArrays &D, hipStream_t s);
+                              const Bases &b, const DArrays &D, int rows, hipStream_t s);
 template <typename T> hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipStream_t s);
 
 // solve sweeps
