@@ -91,6 +91,7 @@ struct d3m_problem {
     DevBuf vec[2][VARR_COUNT];
     int vec_nrhs[2] = {0, 0};
     DevBuf stage_f, stage_E, stage_r, stage_w, stage_g;
+    DevBuf stage_et;  // the field transposed (right-hand sides of an edge contiguous) for the residual
     DevBuf norms;
     double2 *d_unused = nullptr;
     // profiling
@@ -146,7 +147,7 @@ struct d3m_problem {
             for (auto &b : arr[pr]) if (b.p) (void)hipFree(b.p);
             for (auto &b : vec[pr]) if (b.p) (void)hipFree(b.p);
         }
-        for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &norms})
+        for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &stage_et, &norms})
             if (b->p) (void)hipFree(b->p);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         for (auto e : sync_pool) (void)hipEventDestroy(e);
@@ -666,11 +667,12 @@ int residual_inf(d3m_problem *h, const double2 *f, const double2 *E, int nrhs, s
     const size_t n = (size_t)h->n_problems * nrhs;
     int rc = h->ensure(h->norms, sizeof(unsigned long long) * n);
     if (rc) return rc;
+    if ((rc = h->ensure(h->stage_et, sizeof(double2) * (size_t)nrhs * h->mesh.ne))) return rc;
     HIPCHK(hipMemsetAsync(h->norms.p, 0, sizeof(unsigned long long) * n, s));
     hipEvent_t ev{};
     h->prof_begin(KID_RESID, ev, s);
-    HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, h->d_rowptr, h->d_col, h->d_sval, h->d_eprob, h->mesh.ne,
-                           nrhs, (unsigned long long *)h->norms.p, s));
+    HIPCHK(launch_residual((double2 *)h->stage_r.p, f, E, (double2 *)h->stage_et.p, h->d_rowptr, h->d_col, h->d_sval,
+                           h->d_eprob, h->mesh.ne, nrhs, (unsigned long long *)h->norms.p, s));
     h->prof_end(KID_RESID, ev, 0.0, s);
     return fetch_norms(h, (int)n, out, s);
 }

@@ -64,9 +64,9 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
 // r = f - S E; the largest |r| over the rows of each problem (eprob: problem
 // of every row) and right-hand side is folded into nmax[p * nrhs + c]
 // (zeroed by the caller)
-hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, const int32_t *eprob, int64_t ne, int nrhs, unsigned long long *nmax,
-                           hipStream_t s);
+hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, double2 *Et, const int64_t *rowptr,
+                           const int32_t *col, const double2 *val, const int32_t *eprob, int64_t ne, int nrhs,
+                           unsigned long long *nmax, hipStream_t s);
 hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne, int nrhs,
                               hipStream_t s);
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s);

@@ -351,6 +351,22 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
     // lf holds the fragment of the next product; after the last one it takes
     // the fused diagonal solve's TT, whose loads then overlap the last product
     T2 lf[16], xr[4 * NCB];
+    T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
+    const T2 *vin = nullptr;
+    if (fz >= 0 && TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
+    // the target block (and the fused backward solve's v) do not depend on the
+    // products: their loads are issued first, so their latency overlaps them
+    // (except for 32 FP64 columns, whose registers are taken by the products)
+    constexpr bool kPre = !(std::is_same<T, double>::value && NCB == 2);
+    T2 opre[NCB][4], vpre[NCB][4];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * cb + M::out_row(lk, r);
+            opre[cb][r] = kPre && MODE != 1 && c < ncol ? out[c * 64 + m] : T2{0, 0};
+            vpre[cb][r] = kPre && vin && c < ncol ? vin[c * 64 + m] : T2{0, 0};
+        }
     if (tk.np > 0) {
         const VUpdPair pr = pairs[tk.p0];
         sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
@@ -374,9 +390,6 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
         }
         sv_mma<T, NCB>(acc, lc, xs);
     }
-    T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
-    const T2 *vin = nullptr;
-    if (fz >= 0 && TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
     // the buffer not read by the last product (its previous readers passed the last barrier)
     T2 *xd = sm.xs[tk.np & 1];
 #pragma unroll
@@ -386,14 +399,14 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
             const int c = 16 * cb + M::out_row(lk, r);
             T2 nw{0, 0};
             if (c < ncol) {
-                T2 *o = out + c * 64 + m;
                 const double2 res = acc.get(cb, r);
-                if (MODE == 0) nw = from_d2<T2>(csub(to_d2(*o), res));
+                const T2 old = kPre ? opre[cb][r] : (MODE != 1 ? out[c * 64 + m] : T2{0, 0});
+                if (MODE == 0) nw = from_d2<T2>(csub(to_d2(old), res));
                 else if (MODE == 1) nw = from_d2<T2>(res);
-                else nw = from_d2<T2>(cadd(to_d2(*o), res));
-                *o = nw;
+                else nw = from_d2<T2>(cadd(to_d2(old), res));
+                out[c * 64 + m] = nw;
                 // input of the fused diagonal solve: x (forward) or v - acc (backward)
-                if (TR && fz >= 0) nw = from_d2<T2>(csub(to_d2(vin[c * 64 + m]), to_d2(nw)));
+                if (TR && fz >= 0) nw = from_d2<T2>(csub(to_d2(kPre ? vpre[cb][r] : vin[c * 64 + m]), to_d2(nw)));
             }
             if (fz >= 0) xd[c * SV_PQ + m] = nw;
         }
@@ -444,9 +457,10 @@ __global__ void vcollect_kernel(double2 *E, const T2 *X, const int64_t *cmap, in
 // Norm reductions.  nmax[p * nrhs + c] holds the bit pattern of a
 // non-negative double (monotone under unsigned comparison) or of a NaN, which
 // compares above every number, so a NaN anywhere in the data reaches the host.
-// A block covers kRowsPer * 256 consecutive rows; each thread keeps running
-// maxima for its rows and the block combines them in LDS, so a block that
-// lies inside one problem issues one atomic per right-hand side.
+// A block covers consecutive rows (kRowsPer * 256 in the load-norm kernel);
+// each thread keeps running maxima for its rows and the block combines them
+// in LDS, so a block that lies inside one problem issues one atomic per
+// right-hand side.
 constexpr int kRowsPer = 8;
 
 __device__ __forceinline__ double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
@@ -496,58 +510,98 @@ __device__ __forceinline__ void block_fold_max(unsigned long long *nmax, int pcu
     }
 }
 
-// r = f - S E (CSR of the global FEM matrix, FP64).  RES_COLS right-hand sides
-// per block column (blockIdx.y); a thread takes kRowsPer rows 256 apart, and a
-// row's entries are read once for all of its right-hand sides, whose gathers
-// of E are independent of each other.  nmax[p * nrhs + c] (zeroed by the
-// caller) gets the largest |r[c][e]| (modulus) over the rows e of problem
-// p = eprob[e].
-constexpr int RES_COLS = 16;
+// Et[e][c] = E[c][e]: the field with the right-hand sides of one edge
+// contiguous, so that the residual's gathers of a matrix entry's column read
+// 16 right-hand sides as one 256-byte run.  Tiles of 64 edges x 16 columns
+// through LDS; reads and writes coalesced.
+__global__ __launch_bounds__(256) void vtranspose_kernel(double2 *Et, const double2 *E, int64_t ne, int nrhs) {
+    __shared__ double2 tile[16][65];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 16;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = (t >> 6) + 4 * i, r = t & 63;
+        if (r0 + r < ne && c0 + c < nrhs) tile[c][r] = E[(int64_t)(c0 + c) * ne + r0 + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = t + 256 * i, r = idx >> 4, c = idx & 15;
+        if (r0 + r < ne && c0 + c < nrhs) Et[(r0 + r) * nrhs + c0 + c] = tile[c][r];
+    }
+}
 
-__global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *E,
+// r = f - S E (CSR of the global FEM matrix, FP64) from Et.  A block takes
+// RES_ROWS rows and 16 right-hand sides (blockIdx.y); lane l of a wave works
+// on right-hand side l % 16 of row l / 16 of the wave's four current rows, so
+// the gather of Et for one matrix entry is a contiguous 256-byte run shared
+// by 16 lanes.  nmax[p * nrhs + c] (zeroed by the caller) gets the largest
+// |r[c][e]| (modulus) over the rows e of problem p = eprob[e].
+constexpr int RES_ROWS = 256;
+
+__global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *Et,
                                                        const int64_t *rowptr, const int32_t *col, const double2 *val,
                                                        const int32_t *eprob, int64_t ne, int nrhs,
                                                        unsigned long long *nmax) {
-    const int c0 = blockIdx.y * RES_COLS;
-    const int nc = min(RES_COLS, nrhs - c0);
-    const int64_t base = (int64_t)blockIdx.x * 256 * kRowsPer;
+    __shared__ int s_pmin, s_pmax;
+    __shared__ double s_red[16][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane & 15, rs = lane >> 4;
+    const int c0 = blockIdx.y * 16, c = c0 + cl;
+    const int nc = min(16, nrhs - c0);
+    const bool cok = cl < nc;
+    const int64_t base = (int64_t)blockIdx.x * RES_ROWS;
     int pcur = -1;
-    double m[RES_COLS];
-#pragma unroll
-    for (int c = 0; c < RES_COLS; ++c) m[c] = 0.0;
-    for (int i = 0; i < kRowsPer; ++i) {
-        const int64_t row = base + threadIdx.x + 256 * i;
+    double m = 0.0;
+    for (int it = 0; it < RES_ROWS / 16; ++it) {
+        const int64_t row = base + 16 * it + 4 * wave + rs;
         if (row >= ne) break;
         const int p = eprob[row];
-        if (p != pcur) {  // a new problem (batches): fold this thread's maxima so far
-            if (pcur >= 0) {
-#pragma unroll
-                for (int c = 0; c < RES_COLS; ++c)
-                    if (c < nc) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c0 + c], m[c]);
-            }
+        if (p != pcur) {  // a new problem (batches): fold this thread's maximum so far
+            if (pcur >= 0 && cok) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c], m);
             pcur = p;
-#pragma unroll
-            for (int c = 0; c < RES_COLS; ++c) m[c] = 0.0;
+            m = 0.0;
         }
-        double2 s[RES_COLS];
-#pragma unroll
-        for (int c = 0; c < RES_COLS; ++c) s[c] = c < nc ? f[(int64_t)(c0 + c) * ne + row] : make_double2(0, 0);
+        double2 s = cok ? f[(int64_t)c * ne + row] : make_double2(0, 0);
         const int64_t k1 = rowptr[row + 1];
         for (int64_t k = rowptr[row]; k < k1; ++k) {
             const double2 v = val[k];
-            const double2 *Ek = E + (int64_t)c0 * ne + col[k];
-#pragma unroll
-            for (int c = 0; c < RES_COLS; ++c)
-                if (c < nc) s[c] = cfms(s[c], v, Ek[(int64_t)c * ne]);
+            const int64_t j = col[k];
+            if (cok) s = cfms(s, v, Et[j * nrhs + c]);
         }
-#pragma unroll
-        for (int c = 0; c < RES_COLS; ++c)
-            if (c < nc) {
-                r[(int64_t)(c0 + c) * ne + row] = s[c];
-                m[c] = nanmax(m[c], sqrt(s[c].x * s[c].x + s[c].y * s[c].y));
-            }
+        if (cok) {
+            r[(int64_t)c * ne + row] = s;
+            m = nanmax(m, sqrt(s.x * s.x + s.y * s.y));
+        }
     }
-    block_fold_max<RES_COLS>(nmax, pcur, m, nrhs, c0, nc);
+    // one atomic per block and right-hand side when the block lies in one problem
+    if (threadIdx.x == 0) {
+        s_pmin = INT_MAX;
+        s_pmax = -1;
+    }
+    __syncthreads();
+    if (pcur >= 0) {
+        atomicMin(&s_pmin, pcur);
+        atomicMax(&s_pmax, pcur);
+    }
+    __syncthreads();
+    const int pmin = s_pmin, pmax = s_pmax;
+    if (pmax < 0) return;
+    if (pmin == pmax) {
+        double v = cok ? m : 0.0;
+        v = nanmax(v, __shfl_xor(v, 16));
+        v = nanmax(v, __shfl_xor(v, 32));
+        if (lane < 16) s_red[lane][wave] = v;
+        __syncthreads();
+        if ((int)threadIdx.x < nc) {
+            const int cc = threadIdx.x;
+            const double w = nanmax(nanmax(s_red[cc][0], s_red[cc][1]), nanmax(s_red[cc][2], s_red[cc][3]));
+            atomic_max_bits(&nmax[(int64_t)pmin * nrhs + c0 + cc], w);
+        }
+    } else if (pcur >= 0 && cok) {
+        atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c], m);
+    }
 }
 
 // nmax[p * nrhs + c] = max |v[c][e]| over the rows e of problem p (|z| =
@@ -690,11 +744,13 @@ hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64
     return hipGetLastError();
 }
 
-hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, const int64_t *rowptr, const int32_t *col,
-                           const double2 *val, const int32_t *eprob, int64_t ne, int nrhs, unsigned long long *nmax,
-                           hipStream_t s) {
-    dim3 grid(g1(ne, 256 * kRowsPer).x, (unsigned)((nrhs + RES_COLS - 1) / RES_COLS));
-    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, r, f, E, rowptr, col, val, eprob, ne, nrhs, nmax);
+hipError_t launch_residual(double2 *r, const double2 *f, const double2 *E, double2 *Et, const int64_t *rowptr,
+                           const int32_t *col, const double2 *val, const int32_t *eprob, int64_t ne, int nrhs,
+                           unsigned long long *nmax, hipStream_t s) {
+    const unsigned cb = (unsigned)((nrhs + 15) / 16);
+    hipLaunchKernelGGL(vtranspose_kernel, dim3(g1(ne, 64).x, cb), dim3(256), 0, s, Et, E, ne, nrhs);
+    hipLaunchKernelGGL(residual_kernel, dim3(g1(ne, RES_ROWS).x, cb), dim3(256), 0, s, r, f, Et, rowptr, col, val,
+                       eprob, ne, nrhs, nmax);
     return hipGetLastError();
 }
 hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const int32_t *eprob, int64_t ne, int nrhs,
