@@ -52,9 +52,10 @@ __device__ __forceinline__ double2 crecip(double2 z) {
 __device__ __forceinline__ double cabs1(double2 z) { return fabs(z.x) + fabs(z.y); }
 
 
-// Real MFMA products used by the complex tile kernels (four real products per
-// complex one, or three in the FP64 kernels: P1 = Re a Re b, P2 = Im a Im b,
-// P3 = (Re a + Im a)(Re b + Im b), Re = P1 - P2, Im = P3 - P1 - P2).
+// Real MFMA products used by the complex tile kernels (three real products
+// per complex one in the factor kernels and the FP64 solve: P1 = Re a Re b,
+// P2 = Im a Im b, P3 = (Re a + Im a)(Re b + Im b), Re = P1 - P2,
+// Im = P3 - P1 - P2; four in the FP32 solve).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 

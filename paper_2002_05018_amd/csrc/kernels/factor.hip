@@ -588,63 +588,49 @@ __global__ __launch_bounds__(64 * NW) void bk64_kernel(const BkTask *tasks, cons
 
 // ------------------------------------------------- complex GEMM (MFMA) --
 // C (=|-=) sum_p A_p B_p^T for 64x64 complex tiles on real MFMAs (three per
-// complex product in FP64, four in FP32), 256 threads: wave w owns the 32x32 quadrant
+// complex product), 256 threads: wave w owns the 32x32 quadrant
 // (rows 32*(w>>1), cols 32*(w&1)).  The MFMA's first operand is taken from B
 // and its second from A so that the accumulator holds C^T, whose per-lane
 // layout maps to contiguous runs of column-major C.
 
 // One k-step (4 inner indices) of the complex products of a wave's MS x QS
-// sub-tiles of 16 x 16.  FP64 uses three real products per complex one
+// sub-tiles of 16 x 16, with three real products per complex one
 // (P1 = Re w Re x, P2 = Im w Im x, P3 = (Re w + Im w)(Re x + Im x);
 // Re = P1 - P2, Im = P3 - P1 - P2, combined by cmma_finish): a quarter fewer
-// MFMAs than the four-product form, whose rounding (cancellation in Im when it
-// is small next to the operands) stays at the FP64 rounding level.  FP32
-// keeps the four products (re, im accumulate directly; p3 is unused), so that
-// the factors the refinement starts from carry no extra error.
+// MFMAs than four products.  Its rounding (cancellation in Im when Im is small
+// next to the operands) stays at the working precision's level; in FP32 it
+// costs the refinement one more correction at 48^3 hexes, which the faster
+// factorisation more than pays for.
 template <typename T, int MS, int QS>
 __device__ __forceinline__ void cmma_step(const typename C2T<T>::type (&wq)[QS], const typename C2T<T>::type (&xm)[MS],
                                           typename Mfma<T>::acc (&re)[MS][QS], typename Mfma<T>::acc (&im)[MS][QS],
                                           typename Mfma<T>::acc (&p3)[MS][QS]) {
     using M = Mfma<T>;
-    if constexpr (std::is_same<T, double>::value) {
-        T ws[QS], xsum[MS];
+    T ws[QS], xsum[MS];
 #pragma unroll
-        for (int q = 0; q < QS; ++q) ws[q] = wq[q].x + wq[q].y;
+    for (int q = 0; q < QS; ++q) ws[q] = wq[q].x + wq[q].y;
 #pragma unroll
-        for (int m = 0; m < MS; ++m) xsum[m] = xm[m].x + xm[m].y;
+    for (int m = 0; m < MS; ++m) xsum[m] = xm[m].x + xm[m].y;
 #pragma unroll
-        for (int m = 0; m < MS; ++m)
+    for (int m = 0; m < MS; ++m)
 #pragma unroll
-            for (int q = 0; q < QS; ++q) {
-                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
-                im[m][q] = M::mma(wq[q].y, xm[m].y, im[m][q]);
-                p3[m][q] = M::mma(ws[q], xsum[m], p3[m][q]);
-            }
-    } else {
-#pragma unroll
-        for (int m = 0; m < MS; ++m)
-#pragma unroll
-            for (int q = 0; q < QS; ++q) {
-                re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
-                re[m][q] = M::mma(-wq[q].y, xm[m].y, re[m][q]);
-                im[m][q] = M::mma(wq[q].x, xm[m].y, im[m][q]);
-                im[m][q] = M::mma(wq[q].y, xm[m].x, im[m][q]);
-            }
-    }
+        for (int q = 0; q < QS; ++q) {
+            re[m][q] = M::mma(wq[q].x, xm[m].x, re[m][q]);
+            im[m][q] = M::mma(wq[q].y, xm[m].y, im[m][q]);
+            p3[m][q] = M::mma(ws[q], xsum[m], p3[m][q]);
+        }
 }
 template <typename T, int MS, int QS>
 __device__ __forceinline__ void cmma_finish(typename Mfma<T>::acc (&re)[MS][QS], typename Mfma<T>::acc (&im)[MS][QS],
                                             const typename Mfma<T>::acc (&p3)[MS][QS]) {
-    if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-        for (int m = 0; m < MS; ++m)
+    for (int m = 0; m < MS; ++m)
 #pragma unroll
-            for (int q = 0; q < QS; ++q) {
-                const typename Mfma<T>::acc r = re[m][q] - im[m][q];
-                im[m][q] = p3[m][q] - re[m][q] - im[m][q];
-                re[m][q] = r;
-            }
-    }
+        for (int q = 0; q < QS; ++q) {
+            const typename Mfma<T>::acc r = re[m][q] - im[m][q];
+            im[m][q] = p3[m][q] - re[m][q] - im[m][q];
+            re[m][q] = r;
+        }
 }
 
 // Accumulates sum_p A_p B_p^T of one task for the output rows wr + 16 m + i

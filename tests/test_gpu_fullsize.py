@@ -92,8 +92,8 @@ def test_config4_fp64_and_fp32_refinement():
     """Configuration 4 at full size: FP64 relative residual of the
     undecomposed system and reciprocity f_1^T E_2 = f_2^T E_1 on two pairs of
     right-hand sides; FP32 factors with FP64 refinement reach 1e-10 within
-    four corrections (three at this size when measured) and agree with the
-    FP64 solution.  The domain matrices of sampled subdomains are checked
+    four corrections (four at this size when measured, with three-product
+    FP32 tile products) and agree with the FP64 solution.  The domain matrices of sampled subdomains are checked
     against the oracle at configuration 2 (building the oracle's
     decomposition here alone takes about a minute on the host)."""
     prob, s, f = _setup(4)
