@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -734,7 +735,12 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         info->residual = res;
         info->copy_discrepancy = 0.0;
     }
-    if (!ok) return fail(D3M_ENOCONV, "iterative refinement stopped at relative residual " + std::to_string(res));
+    if (!ok) {
+        char msg[96];
+        std::snprintf(msg, sizeof(msg), "iterative refinement stopped at relative residual %.3e after %d steps", res,
+                      it);
+        return fail(D3M_ENOCONV, msg);
+    }
     return D3M_OK;
 }
 
