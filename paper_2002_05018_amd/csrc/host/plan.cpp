@@ -574,12 +574,26 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         st.ndg = (i64)pl.vdiag.size() - st.dg0;
         st.up0 = (i64)pl.vupd.size();
         st.up_mode = 0;
+        // Tile columns are taken S1_BLOCK at a time, as in the factorisation:
+        // rows inside the column's block get its product at once (they are
+        // solved next), rows beyond it receive the products of all the
+        // block's columns in one task at the block's last column (one
+        // read-modify-write of the target instead of one per column).
         for (int d = 0; d < N; ++d) {
             if (j >= pl.TE[d]) continue;
-            for (int a = j + 1; a < pl.T[d]; ++a) {
+            const int j0 = j / S1_BLOCK * S1_BLOCK, je = std::min(j0 + S1_BLOCK, pl.TE[d]) - 1;
+            for (int a = j + 1; a <= je; ++a) {
                 if (!nz[d][a][j]) continue;
                 pl.vupd.push_back({V(V_X, pl.vs1[d] + a), (int32_t)pl.vpairs.size(), 1});
                 pl.vpairs.push_back({E(ARR_M, mslot(d, a, j)), V(V_Y, pl.vs1[d] + j)});
+            }
+            if (j != je) continue;
+            for (int a = je + 1; a < pl.T[d]; ++a) {
+                const int32_t p0 = (int32_t)pl.vpairs.size();
+                for (int c = j0; c <= je; ++c)
+                    if (nz[d][a][c]) pl.vpairs.push_back({E(ARR_M, mslot(d, a, c)), V(V_Y, pl.vs1[d] + c)});
+                const int32_t np = (int32_t)pl.vpairs.size() - p0;
+                if (np > 0) pl.vupd.push_back({V(V_X, pl.vs1[d] + a), p0, np});
             }
         }
         st.nup = (i64)pl.vupd.size() - st.up0;
