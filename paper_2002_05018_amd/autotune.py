@@ -1,8 +1,10 @@
 """Launch-shape autotuner.
 
 Times the factorisation and the solve of an actual handle under candidate
-tunings (``d3m_set_tuning``) and keeps the fastest.  The candidates are the
-launch shapes the schedules expose:
+tunings (``d3m_set_tuning``) and keeps the fastest: parameters of the factor
+schedule are scored by a whole factor + solve step (``s1_block`` also blocks
+the forward sweep over the subdomain factors), those of the solve alone by
+the solve.  The candidates are the launch shapes the schedules expose:
 
 * ``s1_block``: tile columns of a subdomain matrix whose Schur updates beyond
   them are applied together (the depth of the blocked update, i.e. how many
@@ -99,6 +101,10 @@ def autotune(solver, rhs, precision="fp64", space=None, repeats=2, cache=None, l
     def run_factor():
         solver.factor(precision)
 
+    def run_step():
+        solver.factor(precision)
+        solver.solve(rhs, out=out)
+
     def run_solve():
         solver.solve(rhs, out=out)
 
@@ -114,7 +120,7 @@ def autotune(solver, rhs, precision="fp64", space=None, repeats=2, cache=None, l
             cand = dict(best, **{name: v})
             solver.set_tuning(**cand)
             if name in _FACTOR_KEYS:
-                t = _time(run_factor, repeats)
+                t = _time(run_step, repeats)
                 factored_with = fkey(cand)
             else:
                 if factored_with != fkey(cand):
