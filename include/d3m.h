@@ -78,7 +78,8 @@ typedef struct {
     int32_t profile;      /* timing with HIP events for d3m_kernel_stats:
                              0 off, 1 the update GEMM launches only, 2 every
                              kernel group (each timed launch adds a little
-                             overhead; 2 adds about a tenth at config 2)      */
+                             overhead; 2 adds about a tenth on 24^3 hexes
+                             in 64 subdomains)                              */
     double ir_tol;        /* FP32_IR: stop when max over right-hand sides of
                              ||f - S E||_inf / ||f||_inf <= ir_tol (1e-10)   */
     int32_t use_graph;    /* 1: d3m_factor captures its launch sequence into a
