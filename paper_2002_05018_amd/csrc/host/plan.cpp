@@ -758,6 +758,8 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     fuse_sweep(pl.k_fwd, false);
     fuse_sweep(pl.k_bwd, true);
     fuse_sweep(pl.s1_bwd, true);
+    for (VUpdTask &u : pl.vupd)
+        if (u.np > 0) { u.l0 = pl.vpairs[u.p0].l; u.src0 = pl.vpairs[u.p0].src; }
 
     // ------------------------------------------------ algorithmic counts --
     i64 ent = 0;

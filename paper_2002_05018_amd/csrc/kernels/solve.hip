@@ -368,7 +368,7 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
             vpre[cb][r] = kPre && vin && c < ncol ? vin[c * 64 + m] : T2{0, 0};
         }
     if (tk.np > 0) {
-        const VUpdPair pr = pairs[tk.p0];
+        const VUpdPair pr{tk.l0, tk.src0};
         sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
         sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
     } else if (fz >= 0) {

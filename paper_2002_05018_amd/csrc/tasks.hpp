@@ -89,6 +89,7 @@ struct VDiagTask {   // y = TT x and v = D^{-1} y   (forward)  or
 struct VUpdTask {    // out (=|-=|+=) sum_p op(L_p) src_p
     int64_t out;
     int32_t p0, np;
+    int64_t l0, src0;  // pair p0 again, so the first tile loads need no pair-list read
 };
 struct VUpdPair {
     int64_t l, src;
