@@ -99,7 +99,19 @@ typedef struct {
                              updates beyond them are applied together (one
                              read-modify-write of each target per block);
                              0 selects the default 2, at most 16            */
-    int32_t reserved[6];
+    int32_t pivot_fallback; /* 1 (default): with pivot_scope 0, a factorisation
+                             that finds a piece of a block singular (or whose
+                             multipliers exceed growth_limit_log10) is redone
+                             with the whole-block scope of Algorithm 1, which
+                             the handle keeps from then on; 0: report the
+                             error instead                                   */
+    int32_t growth_limit_log10; /* 0 (default): no growth check; otherwise,
+                             with pivot_scope 0 and pivot_fallback, every
+                             factorisation measures max |L-hat_ij| over the
+                             factor of -K (one pass over its off-diagonal
+                             tiles) and falls back to the whole-block scope
+                             when it exceeds 10^growth_limit_log10          */
+    int32_t reserved[4];
 } d3m_options;
 
 typedef struct {
@@ -124,7 +136,26 @@ typedef struct {
     int32_t n_problems;       /* independent problems held (1 unless batched) */
     int64_t array_bytes;      /* device bytes of the factor arrays of one
                                  precision (complex128; half for FP32_IR)     */
-    int32_t reserved[2];
+    double mfma_flops_update; /* the update GEMMs' work as executed: full
+                                 64x64x64 tile products, counted like
+                                 flops_update_gemm (flops_update_gemm divided
+                                 by this is the share of MFMA work that is not
+                                 tile padding or upper halves of diagonal
+                                 tiles)                                       */
+    double bytes_update_gemm; /* least HBM bytes of all update GEMMs of one
+                                 factorisation (complex128; half for FP32):
+                                 per elimination step every distinct operand
+                                 tile read once and every target tile read and
+                                 written once                                 */
+    double solve_vector_bytes;/* least vector bytes moved by the update
+                                 launches of one solve, per right-hand side
+                                 (complex128): per sweep step each distinct
+                                 source block read once, each target read and
+                                 written once; factor bytes are solve_bytes   */
+    int32_t pivot_scope;      /* pivot scope of step 5 in effect (0 pieces of
+                                 at most 64 rows, 1 whole blocks)             */
+    int32_t pivot_fallbacks;  /* factorisations redone with the whole-block
+                                 scope (options.pivot_fallback)               */
 } d3m_info;
 
 typedef struct {
@@ -132,7 +163,13 @@ typedef struct {
     int32_t converged;        /* 1 when the residual test passed             */
     double residual;          /* final max_rhs ||f - S E||_inf / ||f||_inf
                                  (FP64 evaluation; computed for both modes)   */
-    double copy_discrepancy;  /* max |E_d[e] - E_d'[e]| over shared edges     */
+    double copy_discrepancy;  /* max over shared edges e, right-hand sides and
+                                 pairs of subdomain copies of |E_d[e] - E_d'[e]|
+                                 (the recovered subdomain fields of step 7; the
+                                 continuity D^T E = 0 of eq. (1) holds up to
+                                 the rounding of lambda).  FP32_IR: the sum of
+                                 this figure over the solve passes, a bound
+                                 for the refined field                       */
 } d3m_solve_info;
 
 /* Fill `opt` with the defaults listed above. */
@@ -189,9 +226,22 @@ int d3m_update_eps(d3m_handle h, const double *eps_r);
  * elimination of every subdomain into its domain matrix, assembly of K, block
  * LDL^T of K with Bunch-Kaufman pivoting restricted to each diagonal block.
  * precision: D3M_FP64 or D3M_FP32_IR.  Returns after the stream completes.
+ * With pivot_scope 0 and options.pivot_fallback set, a singular piece (or
+ * multipliers beyond options.growth_limit_log10) makes the call re-plan the
+ * handle for whole-block pivoting and factor again (d3m_info.pivot_scope,
+ * .pivot_fallbacks).
  * Errors: D3M_ESINGULAR (a pivot block is singular; d3m_last_error names the
  * block and column; there are no delayed pivots), D3M_ENOMEM, D3M_EHIP. */
 int d3m_factor(d3m_handle h, int precision, void *stream);
+
+/* Growth monitor of the last factorisation: the largest |entry| of the
+ * off-diagonal factor blocks L-hat_ij = X_ij D_jj^{-1} (Algorithm 1; their
+ * size is bounded by no pivoting, since pivots are searched only inside a
+ * diagonal block and none is delayed), over the tile columns of step 1
+ * (lhat_subdomains) and over the units of -K (lhat_k).  One pass over those
+ * tiles on the default stream; synchronous.  NULL outputs are skipped.
+ * Errors: D3M_ESTATE (not factored), D3M_EHIP. */
+int d3m_factor_growth(d3m_handle h, double *lhat_subdomains, double *lhat_k);
 
 /* Recipe steps 6-7: E = S^{-1} f for nrhs right-hand sides.
  *   rhs  [nrhs][n_edges] complex128 (global load f, row per right-hand side).
@@ -332,6 +382,49 @@ int d3m_kernel_stats(d3m_handle h, int kernel, int reset, int64_t *launches,
 #define D3M_EXPORT_LAMBDA    10
 int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf,
                          int64_t bytes);
+
+/* ---- test hook: the Bunch-Kaufman kernels on caller blocks ---------------
+ * Runs the kernels that factor the diagonal blocks of step 5 (the first line
+ * of Algorithm 1: P^T K_jj P = L D L^T with Bunch-Kaufman 1x1/2x2 pivoting
+ * restricted to the block, no delayed pivots) and the diagonal tiles of
+ * step 1 on `count` independent blocks of order n, so that their pivot
+ * decisions and outputs can be compared with a reference one by one.
+ *   a         [count][n][n] host, row-major complex symmetric blocks (only
+ *             the lower triangle is read)
+ *   n         1..1024
+ *   precision D3M_FP64 (blocks stored in complex128) or D3M_FP32_IR (stored
+ *             in complex64: the input is rounded to it; the pivot search, D
+ *             and D^{-1} stay FP64 as in the factorisation)
+ *   variant   0 the kernel d3m_factor uses for this order (register kernel
+ *             for n <= 64, else the general kernel with the block in LDS if
+ *             it fits, else in global memory); 1 the general kernel with the
+ *             block in LDS (D3M_EINVAL if it does not fit); 2 the general
+ *             kernel with the block in global memory
+ *   device    HIP device ordinal
+ * Outputs (host arrays owned by the caller; any pointer may be NULL):
+ *   L        [count][n][n] row-major unit lower L of P^T A P (upper zero)
+ *   d, doff  [count][n] diagonal of D and the off-diagonal of each 2x2 pivot
+ *            (stored on both of its rows; 0 for 1x1 pivots)
+ *   dinv, dinvoff [count][n] the same for D^{-1}
+ *   kind     [count][n] 0: 1x1 pivot, 1: first row of a 2x2, -1: second row
+ *   perm     [count][n] (P^T A P)[i][j] = A[perm[i]][perm[j]]
+ *   tt       [count][n][n] row-major L^{-1} P^T (what the sweeps apply)
+ *   singular [count] 0, or 1 + the column at which no pivot was found
+ * Returns D3M_ESINGULAR (naming the first singular block and column) when a
+ * block has a zero column; the outputs of the other blocks are still
+ * written.  Allocates and frees its own device memory.  Errors: D3M_EINVAL,
+ * D3M_ENODEV, D3M_ENOMEM, D3M_EHIP. */
+typedef struct {
+    d3m_c128 *L;
+    d3m_c128 *d, *doff;
+    d3m_c128 *dinv, *dinvoff;
+    int32_t *kind;
+    int32_t *perm;
+    d3m_c128 *tt;
+    int32_t *singular;
+} d3m_bk_out;
+int d3m_debug_bk(const d3m_c128 *a, int32_t n, int32_t count, int precision,
+                 int variant, int device, d3m_bk_out *out);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,7 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
-                    "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"]
+                    "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth"]
 
 
 class d3m_c128(C.Structure):
@@ -57,7 +57,7 @@ class d3m_options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("quad_points", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
                 ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32), ("s1_block", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("pivot_fallback", C.c_int32), ("growth_limit_log10", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class d3m_info(C.Structure):
@@ -67,7 +67,9 @@ class d3m_info(C.Structure):
                 ("flops_domain", C.c_double), ("flops_block_ldlt", C.c_double),
                 ("flops_update_gemm", C.c_double), ("solve_bytes", C.c_double),
                 ("factored", C.c_int32), ("n_units", C.c_int32), ("n_unit_levels", C.c_int32),
-                ("n_problems", C.c_int32), ("array_bytes", C.c_int64), ("reserved", C.c_int32 * 2)]
+                ("n_problems", C.c_int32), ("array_bytes", C.c_int64), ("mfma_flops_update", C.c_double),
+                ("bytes_update_gemm", C.c_double), ("solve_vector_bytes", C.c_double),
+                ("pivot_scope", C.c_int32), ("pivot_fallbacks", C.c_int32)]
 
 
 class d3m_batch_item(C.Structure):
@@ -78,6 +80,12 @@ class d3m_tuning(C.Structure):
     _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
                 ("k_block", C.c_int32), ("side_early", C.c_int32), ("k_fuse", C.c_int32),
                 ("panel_rows", C.c_int32), ("reserved", C.c_int32 * 1)]
+
+
+class d3m_bk_out(C.Structure):
+    _fields_ = [("L", C.c_void_p), ("d", C.c_void_p), ("doff", C.c_void_p), ("dinv", C.c_void_p),
+                ("dinvoff", C.c_void_p), ("kind", C.c_void_p), ("perm", C.c_void_p), ("tt", C.c_void_p),
+                ("singular", C.c_void_p)]
 
 
 class d3m_solve_info(C.Structure):
@@ -113,6 +121,10 @@ _lib.d3m_kernel_stats.argtypes = [_h, C.c_int, C.c_int, C.POINTER(C.c_int64), C.
 _lib.d3m_debug_export.argtypes = [_h, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
 _lib.d3m_debug_export.restype = C.c_int64
 _lib.d3m_set_profile.argtypes = [_h, C.c_int]
+_lib.d3m_debug_bk.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_int, C.c_int, C.POINTER(d3m_bk_out)]
+_lib.d3m_debug_bk.restype = C.c_int
+_lib.d3m_factor_growth.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+_lib.d3m_factor_growth.restype = C.c_int
 for _f in ("d3m_setup", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch", "d3m_update_eps",
            "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
            "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"):
@@ -146,7 +158,7 @@ def _stream_handle(stream):
 
 
 def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10,
-             pivot_scope=0, s1_block=0, use_graph=False):
+             pivot_scope=0, s1_block=0, use_graph=False, pivot_fallback=True, growth_limit_log10=0):
     opt = d3m_options()
     _lib.d3m_default_options(C.byref(opt))
     opt.host_only = int(host_only)
@@ -159,7 +171,45 @@ def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol
     opt.pivot_scope = int(pivot_scope)
     opt.s1_block = int(s1_block)
     opt.use_graph = int(use_graph)
+    opt.pivot_fallback = int(bool(pivot_fallback))
+    opt.growth_limit_log10 = int(growth_limit_log10)
     return opt
+
+
+def _check_like(t, ref, name):
+    """t must be a contiguous tensor of ref's shape, dtype and device (the
+    library writes or reads nrhs * n_edges * 16 bytes through its pointer)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != ref.dtype or tuple(t.shape) != tuple(ref.shape) \
+            or t.device != ref.device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {ref.dtype} tensor of shape {tuple(ref.shape)} "
+                         f"on {ref.device}")
+
+
+def debug_bk(blocks, precision=FP64, variant=0, device=0):
+    """Run the library's Bunch-Kaufman kernels on blocks [count, n, n]
+    (complex symmetric; d3m_debug_bk).  Returns (status, outputs) where
+    outputs holds L, d, doff, dinv, dinvoff, kind, perm, tt, singular as numpy
+    arrays; status is 0 or the D3M_ESINGULAR code (other errors raise)."""
+    a = np.ascontiguousarray(blocks, dtype=np.complex128)
+    if a.ndim == 2:
+        a = a[None]
+    if a.ndim != 3 or a.shape[1] != a.shape[2]:
+        raise ValueError("blocks must be [count, n, n]")
+    count, n = a.shape[0], a.shape[1]
+    res = {"L": np.zeros((count, n, n), np.complex128), "d": np.zeros((count, n), np.complex128),
+           "doff": np.zeros((count, n), np.complex128), "dinv": np.zeros((count, n), np.complex128),
+           "dinvoff": np.zeros((count, n), np.complex128), "kind": np.zeros((count, n), np.int32),
+           "perm": np.zeros((count, n), np.int32), "tt": np.zeros((count, n, n), np.complex128),
+           "singular": np.zeros(count, np.int32)}
+    out = d3m_bk_out(*[C.c_void_p(res[k].ctypes.data) for k, _ in d3m_bk_out._fields_])
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32_ir": FP32_IR}[precision]
+    rc = _lib.d3m_debug_bk(C.c_void_p(a.ctypes.data), n, count, int(precision), int(variant), int(device),
+                           C.byref(out))
+    if rc not in (0, -2):
+        _check(rc)
+    return rc, res
 
 
 class Solver:
@@ -205,6 +255,10 @@ class Solver:
 
     def _adopt(self, h, k, opt):
         self._handle = h
+        # bumped whenever the factors held by the handle may change (new
+        # eps_r, a factorisation, a re-planned schedule): lets the autograd
+        # backward tell whether the factors are still those of its forward
+        self.generation = 0
         self.k = float(k)
         self.host_only = bool(opt.host_only)
         self.info = self.query()
@@ -229,12 +283,16 @@ class Solver:
     # ---- steps -------------------------------------------------------------
     def update_eps(self, eps_r):
         eps = np.ascontiguousarray(eps_r, dtype=np.float64)
+        if eps.shape != (self.n_tets,):
+            raise ValueError(f"eps_r must be float64 [{self.n_tets}]")
+        self.generation += 1
         _check(_lib.d3m_update_eps(self._handle, _ptr(eps, C.c_double)))
 
     def factor(self, precision=FP64, stream=None):
         if isinstance(precision, str):
             precision = {"fp64": FP64, "fp32_ir": FP32_IR}[precision]
         hs = C.c_void_p(0) if self.host_only else _stream_handle(stream)
+        self.generation += 1
         _check(_lib.d3m_factor(self._handle, int(precision), hs))
 
     def solve(self, rhs, out=None, stream=None, with_info=False):
@@ -248,6 +306,8 @@ class Solver:
             raise ValueError("rhs must be complex128 [nrhs, n_edges]")
         if out is None:
             out = torch.empty_like(rhs)
+        else:
+            _check_like(out, rhs, "out")
         info = d3m_solve_info()
         rc = _lib.d3m_solve(self._handle, C.c_void_p(rhs.data_ptr()), rhs.shape[0],
                             C.c_void_p(out.data_ptr()), C.byref(info) if with_info else None,
@@ -255,13 +315,19 @@ class Solver:
         _check(rc)
         if with_info:
             return out, {"iterations": info.iterations, "converged": bool(info.converged),
-                         "residual": info.residual}
+                         "residual": info.residual, "copy_discrepancy": info.copy_discrepancy}
         return out
 
     def adjoint(self, grad_E, E, want_w=False, stream=None):
         import torch
+        if not isinstance(grad_E, torch.Tensor) or grad_E.dtype != torch.complex128 or grad_E.dim() != 2 \
+                or grad_E.shape[1] != self.n_edges:
+            raise ValueError("grad_E must be a complex128 tensor [nrhs, n_edges]")
         grad_E = grad_E.contiguous()
+        if not isinstance(E, torch.Tensor):
+            raise ValueError("E must be a complex128 tensor [nrhs, n_edges]")
         E = E.contiguous()
+        _check_like(E, grad_E, "E")
         dev = grad_E.device
         grad = torch.empty(self.n_tets, dtype=torch.float64, device=dev)
         w = torch.empty_like(grad_E) if want_w else None
@@ -308,6 +374,14 @@ class Solver:
                               _ptr(coef, C.c_double)))
         return edges, coef
 
+    def growth(self):
+        """(max |L-hat| of step 1, max |L-hat| of -K) of the last factorisation
+        (d3m_factor_growth)."""
+        a = C.c_double()
+        b = C.c_double()
+        _check(_lib.d3m_factor_growth(self._handle, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def query(self):
         inf = d3m_info()
         _check(_lib.d3m_query(self._handle, C.byref(inf)))
@@ -334,6 +408,7 @@ class Solver:
             if k not in self.TUNING_KEYS:
                 raise KeyError(k)
             setattr(t, k, int(v))
+        self.generation += 1
         _check(_lib.d3m_set_tuning(self._handle, C.byref(t)))
 
     def set_profile(self, level):

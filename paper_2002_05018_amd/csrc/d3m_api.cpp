@@ -77,6 +77,11 @@ struct d3m_problem {
     int64_t *d_coo_off = nullptr;
     double2 *d_coo_val = nullptr;
     int64_t *d_split = nullptr, *d_collect = nullptr, *d_hmap = nullptr, *d_lmap = nullptr;
+    int64_t *d_copymap = nullptr;
+    unsigned long long *d_disc = nullptr;
+    FactorTile *d_lhat_s1 = nullptr, *d_lhat_k = nullptr;
+    unsigned long long *d_growth = nullptr;
+    int pivot_fallbacks = 0;  // factorisations redone with whole-block pivot scope
     int *d_status = nullptr;
     DArrays D{};
     double2 *d_bkscratch = nullptr;
@@ -291,6 +296,9 @@ int upload_schedules(d3m_problem *h, bool replace) {
     UPS(h->d_coo_off, pl.coo_off);
     UPS(h->d_split, pl.split_map);
     UPS(h->d_collect, pl.collect_map);
+    UPS(h->d_copymap, pl.copy_map);
+    UPS(h->d_lhat_s1, pl.lhat_s1);
+    UPS(h->d_lhat_k, pl.lhat_k);
     UPS(h->d_hmap, pl.h_map);
     UPS(h->d_lmap, pl.lam_map);
 #undef UPS
@@ -690,6 +698,25 @@ double relative_residual(const std::vector<double> &rn, const std::vector<double
     return res;
 }
 
+// largest |difference| between subdomain copies of a shared edge in the
+// subdomain vectors of the last solve pass of precision T (the continuity
+// D^T E = 0 of eq. (1) holds up to the rounding of lambda)
+template <typename T>
+int copy_discrepancy(d3m_problem *h, int nrhs, double &out, hipStream_t s) {
+    if (!h->d_disc) {
+        int rc = h->zeros(h->d_disc, sizeof(unsigned long long));
+        if (rc != D3M_OK) return rc;
+    }
+    HIPCHK(hipMemsetAsync(h->d_disc, 0, sizeof(unsigned long long), s));
+    VBases vb = vbases_of<T>(h);
+    HIPCHK(launch_copy_disc<T>(h->d_disc, vb.p[V_X], h->d_copymap, h->pl.v_tiles_s1 * 64, nrhs, s));
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, h->d_disc, sizeof(bits), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(&out, &bits, sizeof(double));
+    return D3M_OK;
+}
+
 // full solve on device buffers (both precisions); optional diagnostics
 int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_solve_info *info, hipStream_t s) {
     const size_t vbytes = sizeof(double2) * (size_t)nrhs * h->mesh.ne;
@@ -705,7 +732,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
             info->iterations = 0;
             info->converged = res == res ? 1 : 0;  // a NaN residual passes no test
             info->residual = res;
-            info->copy_discrepancy = 0.0;
+            if ((rc = copy_discrepancy<double>(h, nrhs, info->copy_discrepancy, s))) return rc;
         }
         HIPCHK(hipStreamSynchronize(s));
         h->prof_collect();
@@ -716,6 +743,10 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     std::vector<double> fn, rn;
     if ((rc = norms_inf(h, f, nrhs, fn, s))) return rc;
     if ((rc = solve_pass<float>(h, f, E, nrhs, false, s))) return rc;
+    // E is the sum of the passes' fields, so the sum of their copy
+    // discrepancies bounds that of E
+    double disc = 0.0, d1 = 0.0;
+    if (info && (rc = copy_discrepancy<float>(h, nrhs, disc, s))) return rc;
     int it = 0;
     double res = 0.0;
     bool ok = false;
@@ -725,6 +756,10 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         if (res <= h->opt.ir_tol) { ok = true; break; }
         if (it >= h->opt.ir_max_iter) break;
         if ((rc = solve_pass<float>(h, (double2 *)h->stage_r.p, E, nrhs, true, s))) return rc;
+        if (info) {
+            if ((rc = copy_discrepancy<float>(h, nrhs, d1, s))) return rc;
+            disc += d1;
+        }
         ++it;
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -733,7 +768,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         info->iterations = it;
         info->converged = ok ? 1 : 0;
         info->residual = res;
-        info->copy_discrepancy = 0.0;
+        info->copy_discrepancy = disc;
     }
     if (!ok) {
         char msg[96];
@@ -747,6 +782,66 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
 }  // namespace
 
 namespace {
+
+// max |L-hat| over the off-diagonal factor tiles of step 1 and of -K of the
+// factors of precision T (one pass over those tiles; synchronous on s)
+template <typename T>
+int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
+    if (!h->d_growth) {
+        int rc = h->zeros(h->d_growth, 2 * sizeof(unsigned long long));
+        if (rc != D3M_OK) return rc;
+    }
+    HIPCHK(hipMemsetAsync(h->d_growth, 0, 2 * sizeof(unsigned long long), s));
+    Bases b = bases_of<T>(h);
+    HIPCHK(launch_growth<T>(h->d_lhat_s1, (int64_t)h->pl.lhat_s1.size(), b, h->d_growth, s));
+    HIPCHK(launch_growth<T>(h->d_lhat_k, (int64_t)h->pl.lhat_k.size(), b, h->d_growth + 1, s));
+    unsigned long long bits[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bits, h->d_growth, sizeof(bits), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(&s1, &bits[0], sizeof(double));
+    std::memcpy(&k, &bits[1], sizeof(double));
+    return D3M_OK;
+}
+
+// Re-plans the handle for another pivot scope of step 5 (0: pieces of at most
+// 64 rows, 1: whole blocks as in Algorithm 1).  The units, and with them the
+// schedules, the pivot data of K and its storage, change; the factors are
+// dropped.
+int replan_scope(d3m_problem *h, int scope) {
+    Plan np;
+    try {
+        build_plan(np, h->dc, h->bo, scope == 1 ? 0 : TILE, h->tune.s1_block, h->tune.k_block, h->tune.k_fuse != 0);
+    } catch (const Error &e) {
+        return fail(D3M_EINVAL, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(D3M_ENOMEM, "host allocation failed in re-planning");
+    }
+    h->drop_graphs();
+    const i64 old_status = h->pl.n_status, old_rows = h->pl.d_rows, old_scr = h->pl.bk_scratch_elems;
+    h->pl = std::move(np);
+    h->opt.pivot_scope = scope;
+    h->factored = 0;
+    h->vec_nrhs[0] = h->vec_nrhs[1] = 0;  // vector layouts are sized again on the next solve
+    if (!h->device_ready) return D3M_OK;
+    int rc;
+    if ((rc = upload_schedules(h, true)) != D3M_OK) return rc;
+    const Plan &pl = h->pl;
+    if (pl.n_status > old_status && (rc = h->zeros(h->d_status, sizeof(int) * (pl.n_status + 1))) != D3M_OK)
+        return rc;
+    if (pl.d_rows > old_rows) {
+        const size_t dr = (size_t)pl.d_rows;
+        if ((rc = h->zeros(h->D.d, dr * sizeof(double2))) != D3M_OK) return rc;
+        if ((rc = h->zeros(h->D.doff, dr * sizeof(double2))) != D3M_OK) return rc;
+        if ((rc = h->zeros(h->D.dinv, dr * sizeof(double2))) != D3M_OK) return rc;
+        if ((rc = h->zeros(h->D.dinvoff, dr * sizeof(double2))) != D3M_OK) return rc;
+        if ((rc = h->zeros(h->D.piv, dr * sizeof(int))) != D3M_OK) return rc;
+        if ((rc = h->zeros(h->D.perm, dr * sizeof(int))) != D3M_OK) return rc;
+    }
+    if (pl.bk_scratch_elems > old_scr &&
+        (rc = h->zeros(h->d_bkscratch, (size_t)pl.bk_scratch_elems * sizeof(double2))) != D3M_OK)
+        return rc;
+    return D3M_OK;
+}
 
 // Host setup of a handle (mesh, decomposition, ordering, plan), then the
 // device upload.  sub_group: problem of every subdomain (empty: one problem).
@@ -881,6 +976,7 @@ void d3m_default_options(d3m_options *o) {
     o->quad_points = 12;
     o->ir_max_iter = 10;
     o->ir_tol = 1e-10;
+    o->pivot_fallback = 1;
 }
 
 
@@ -1004,11 +1100,40 @@ int d3m_factor(d3m_handle h, int precision, void *stream) {
     HIPCHK(hipSetDevice(h->opt.device));
     int rc;
     h->factored = 0;
-    if (precision == D3M_FP64) rc = factor_impl<double>(h, s);
-    else if (precision == D3M_FP32_IR) rc = factor_impl<float>(h, s);
-    else return fail(D3M_EINVAL, "unknown precision");
+    if (precision != D3M_FP64 && precision != D3M_FP32_IR) return fail(D3M_EINVAL, "unknown precision");
+    auto run = [&]() { return precision == D3M_FP64 ? factor_impl<double>(h, s) : factor_impl<float>(h, s); };
+    rc = run();
+    if (h->opt.pivot_scope == 0 && h->opt.pivot_fallback) {
+        // a piece of a block singular, or its multipliers grown past the
+        // limit: factor again with the pivot search over whole blocks
+        bool redo = rc == D3M_ESINGULAR;
+        if (rc == D3M_OK && h->opt.growth_limit_log10 != 0) {
+            double g1 = 0.0, gk = 0.0;
+            const int rg = precision == D3M_FP64 ? factor_growth<double>(h, g1, gk, s)
+                                                 : factor_growth<float>(h, g1, gk, s);
+            if (rg != D3M_OK) return rg;
+            redo = !(gk <= std::pow(10.0, h->opt.growth_limit_log10));
+        }
+        if (redo) {
+            if ((rc = replan_scope(h, 1)) != D3M_OK) return rc;
+            ++h->pivot_fallbacks;
+            rc = run();
+        }
+    }
     if (rc == D3M_OK) h->factored = precision == D3M_FP64 ? 1 : 2;
     return rc;
+}
+
+int d3m_factor_growth(d3m_handle h, double *lhat_subdomains, double *lhat_k) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (!h->factored) return fail(D3M_ESTATE, "growth before factor");
+    HIPCHK(hipSetDevice(h->opt.device));
+    double g1 = 0.0, gk = 0.0;
+    const int rc = h->factored == 1 ? factor_growth<double>(h, g1, gk, nullptr) : factor_growth<float>(h, g1, gk, nullptr);
+    if (rc != D3M_OK) return rc;
+    if (lhat_subdomains) *lhat_subdomains = g1;
+    if (lhat_k) *lhat_k = gk;
+    return D3M_OK;
 }
 
 int d3m_solve(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E, d3m_solve_info *info, void *stream) {
@@ -1156,6 +1281,11 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->n_unit_levels = h->pl.k_levels;
     info->n_problems = h->n_problems;
     info->array_bytes = (2 * h->pl.m_tiles + 3 * h->pl.k_tiles + h->pl.tt_tiles) * (int64_t)TILE_ELEMS * 16;
+    info->mfma_flops_update = h->pl.mfma_flops_update;
+    info->bytes_update_gemm = (double)h->pl.update_min_tiles * TILE_ELEMS * 16.0;
+    info->pivot_scope = h->opt.pivot_scope;
+    info->pivot_fallbacks = h->pivot_fallbacks;
+    info->solve_vector_bytes = (double)h->pl.solve_min_vblocks * TILE * 16.0;
     return D3M_OK;
 }
 
@@ -1304,6 +1434,118 @@ int64_t d3m_debug_export(d3m_handle h, int what, int64_t index, void *buf, int64
         std::memcpy(buf, out.data(), out.size());
     }
     return (int64_t)out.size();
+}
+
+// Test hook: the Bunch-Kaufman kernels of the factorisation on caller blocks.
+int d3m_debug_bk(const d3m_c128 *a, int32_t n, int32_t count, int precision, int variant, int device,
+                 d3m_bk_out *out) {
+    if (!a || !out || n < 1 || n > 1024 || count < 1) return fail(D3M_EINVAL, "bad block arguments");
+    if (precision != D3M_FP64 && precision != D3M_FP32_IR) return fail(D3M_EINVAL, "unknown precision");
+    if (variant < 0 || variant > 2) return fail(D3M_EINVAL, "variant must be 0, 1 or 2");
+    if (variant == 1 && bk_lds_bytes(n, ((n + 63) / 64) * 64, true) > 160 * 1024 - 256)
+        return fail(D3M_EINVAL, "block too large for the LDS variant");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+        return fail(D3M_ENODEV, "no such HIP device");
+    HIPCHK(hipSetDevice(device));
+    const bool f32 = precision == D3M_FP32_IR;
+    const size_t es = f32 ? 8 : 16;
+    const int t = (n + TILE - 1) / TILE;
+    const size_t blk = (size_t)t * t * TILE_ELEMS;  // tile elements per block
+    const size_t ne = blk * count;
+    // host staging in the kernels' tile layout: tile (b, c) of block q at
+    // q*blk + (c*t + b)*4096, column-major inside a tile
+    std::vector<double2> A(ne, make_double2(0, 0));
+    for (int q = 0; q < count; ++q)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) {
+                const d3m_c128 v = a[((size_t)q * n + i) * n + j];
+                A[q * blk + ((size_t)(j / TILE) * t + i / TILE) * TILE_ELEMS + (j % TILE) * TILE + i % TILE] =
+                    make_double2(v.re, v.im);
+            }
+    std::vector<float2> Af;
+    if (f32) {
+        Af.resize(ne);
+        for (size_t e = 0; e < ne; ++e) Af[e] = make_float2((float)A[e].x, (float)A[e].y);
+    }
+    std::vector<BkTask> tasks(count);
+    for (int q = 0; q < count; ++q) {
+        BkTask &k = tasks[q];
+        std::memset(&k, 0, sizeof(k));
+        k.a = enc(ARR_M, (int64_t)(q * blk));
+        k.l = enc(ARR_KL, (int64_t)(q * blk));
+        k.tt = enc(ARR_TT, (int64_t)(q * blk));
+        k.drow = (int64_t)q * n;
+        k.n = n;
+        k.ldt = (int32_t)((size_t)t * TILE_ELEMS);
+        k.status = q;
+    }
+    struct Mem {
+        std::vector<void *> ps;
+        ~Mem() { for (void *p : ps) (void)hipFree(p); }
+        hipError_t get(void **p, size_t bytes) {
+            hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+            if (e == hipSuccess) ps.push_back(*p);
+            return e;
+        }
+    } mem;
+    void *dA, *dL, *dT, *dtask, *dstat, *dscr = nullptr;
+    void *dd[4], *dpiv, *dperm;
+    HIPCHK(mem.get(&dA, ne * es));
+    HIPCHK(mem.get(&dL, ne * es));
+    HIPCHK(mem.get(&dT, ne * es));
+    HIPCHK(mem.get(&dtask, sizeof(BkTask) * count));
+    HIPCHK(mem.get(&dstat, sizeof(int) * count));
+    for (int x = 0; x < 4; ++x) HIPCHK(mem.get(&dd[x], sizeof(double2) * n * count));
+    HIPCHK(mem.get(&dpiv, sizeof(int) * n * count));
+    HIPCHK(mem.get(&dperm, sizeof(int) * n * count));
+    if (n > 64 || variant != 0) HIPCHK(mem.get(&dscr, sizeof(double2) * ((size_t)n * (n + 1) / 2) * count));
+    HIPCHK(hipMemcpy(dA, f32 ? (const void *)Af.data() : (const void *)A.data(), ne * es, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(dL, 0, ne * es));
+    HIPCHK(hipMemset(dT, 0, ne * es));
+    HIPCHK(hipMemset(dstat, 0, sizeof(int) * count));
+    HIPCHK(hipMemcpy(dtask, tasks.data(), sizeof(BkTask) * count, hipMemcpyHostToDevice));
+    Bases b{};
+    b.p[ARR_M] = dA;
+    b.p[ARR_KL] = dL;
+    b.p[ARR_TT] = dT;
+    DArrays D{(double2 *)dd[0], (double2 *)dd[1], (double2 *)dd[2], (double2 *)dd[3], (int *)dpiv, (int *)dperm};
+    if (f32) HIPCHK(launch_bk<float>((const BkTask *)dtask, count, n, nullptr, b, D, (int *)dstat,
+                                     (double2 *)dscr, nullptr, variant));
+    else HIPCHK(launch_bk<double>((const BkTask *)dtask, count, n, nullptr, b, D, (int *)dstat,
+                                  (double2 *)dscr, nullptr, variant));
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<int> st(count);
+    HIPCHK(hipMemcpy(st.data(), dstat, sizeof(int) * count, hipMemcpyDeviceToHost));
+    auto tile_val = [&](const std::vector<double2> &src, const std::vector<float2> &srcf, int q, int i, int j) {
+        const size_t e = q * blk + ((size_t)(j / TILE) * t + i / TILE) * TILE_ELEMS + (j % TILE) * TILE + i % TILE;
+        return f32 ? d3m_c128{srcf[e].x, srcf[e].y} : d3m_c128{src[e].x, src[e].y};
+    };
+    if (out->L || out->tt) {
+        std::vector<double2> h(f32 ? 0 : ne);
+        std::vector<float2> hf(f32 ? ne : 0);
+        for (int which = 0; which < 2; ++which) {
+            d3m_c128 *dst = which == 0 ? out->L : out->tt;
+            if (!dst) continue;
+            HIPCHK(hipMemcpy(f32 ? (void *)hf.data() : (void *)h.data(), which == 0 ? dL : dT, ne * es,
+                             hipMemcpyDeviceToHost));
+            for (int q = 0; q < count; ++q)
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j)
+                        dst[((size_t)q * n + i) * n + j] = (which == 0 && j > i) ? d3m_c128{0, 0} : tile_val(h, hf, q, i, j);
+        }
+    }
+    d3m_c128 *douts[4] = {out->d, out->doff, out->dinv, out->dinvoff};
+    for (int x = 0; x < 4; ++x)
+        if (douts[x]) HIPCHK(hipMemcpy(douts[x], dd[x], sizeof(double2) * n * count, hipMemcpyDeviceToHost));
+    if (out->kind) HIPCHK(hipMemcpy(out->kind, dpiv, sizeof(int) * n * count, hipMemcpyDeviceToHost));
+    if (out->perm) HIPCHK(hipMemcpy(out->perm, dperm, sizeof(int) * n * count, hipMemcpyDeviceToHost));
+    if (out->singular) std::memcpy(out->singular, st.data(), sizeof(int) * count);
+    for (int q = 0; q < count; ++q)
+        if (st[q] != 0)
+            return fail(D3M_ESINGULAR, "singular pivot block: block " + std::to_string(q) + ", column " +
+                                           std::to_string(st[q] - 1));
+    return D3M_OK;
 }
 
 }  // extern "C"

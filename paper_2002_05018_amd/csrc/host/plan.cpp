@@ -11,6 +11,7 @@
 // E_d = A_d^{-1}(f_d - D_d lambda).
 #include <algorithm>
 #include <map>
+#include <unordered_set>
 
 #include "plan.hpp"
 
@@ -531,6 +532,14 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         int d = dc.owner[e];
         pl.collect_map[e] = pl.vs1[d] * TILE + dc.sub[d].row_of((i64)e);
     }
+    pl.copy_map.assign(pl.v_tiles_s1 * TILE, -1);
+    for (int d = 0; d < N; ++d) {
+        const Subdomain &S = dc.sub[d];
+        for (i64 r = 0; r < S.n; ++r) {
+            const i64 e = S.edges[r];
+            if (dc.owner[e] != d) pl.copy_map[pl.vs1[d] * TILE + r] = pl.collect_map[e];
+        }
+    }
     // multiplier rows: K vector row <-> the two subdomain copies
     std::vector<i64> &kvrow_of_lm = pl.lm_vrow;
     kvrow_of_lm.assign(dc.n_lm, -1);
@@ -773,6 +782,49 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     }
     pl.factor_entries = ent;
     pl.solve_bytes = 2.0 * 16.0 * (double)ent;
+    // off-diagonal factor tiles (L-hat = X D^{-1}) for the growth monitor
+    pl.lhat_s1.clear();
+    pl.lhat_k.clear();
+    for (int d = 0; d < N; ++d)
+        for (int j = 0; j < pl.TE[d]; ++j)
+            for (int a = j + 1; a < pl.T[d]; ++a)
+                if (nz[d][a][j])
+                    pl.lhat_s1.push_back({E(ARR_M, mslot(d, a, j)), (int32_t)mrows(d, a), (int32_t)mrows(d, j)});
+    for (int j = 0; j < nb; ++j)
+        for (int i : ustruct[j])
+            for (int a = 0; a < pl.kt[i]; ++a)
+                for (int b = 0; b < pl.kt[j]; ++b)
+                    pl.lhat_k.push_back({E(ARR_KL, kslot(j, i, a, b)), (int32_t)tile_rows(nsz[i], a),
+                                         (int32_t)tile_rows(nsz[j], b)});
+    // every pair of an update task is one full 64x64x64 complex tile product
+    // (8 flops per complex multiply-add), whatever the rows actually used
+    pl.mfma_flops_update = 0.0;
+    pl.update_min_tiles = 0;
+    for (const auto *steps : {&pl.s1_steps, &pl.k_steps})
+        for (const FactorStep &st : *steps) {
+            // least HBM traffic of a step's updates: every distinct operand
+            // tile read once, every target tile read and written once
+            std::unordered_set<i64> ops;
+            for (i64 g = st.up0; g < st.up0 + st.nup; ++g) {
+                pl.mfma_flops_update += 8.0 * TILE * (double)TILE * TILE * pl.gemm[g].np;
+                for (int32_t q = pl.gemm[g].p0; q < pl.gemm[g].p0 + pl.gemm[g].np; ++q) {
+                    ops.insert(pl.pairs[q].a);
+                    ops.insert(pl.pairs[q].b);
+                }
+            }
+            pl.update_min_tiles += (i64)ops.size() + 2 * st.nup;
+        }
+    // vector blocks (64 rows x nrhs) the solve's update launches must move at
+    // least: each distinct source block of a sweep step read once, each
+    // target read and written once
+    pl.solve_min_vblocks = 0;
+    for (const auto *steps : {&pl.s1_fwd, &pl.k_fwd, &pl.k_bwd, &pl.s1_bwd})
+        for (const SolveStep &st : *steps) {
+            std::unordered_set<i64> src;
+            for (i64 u = st.up0; u < st.up0 + st.nup; ++u)
+                for (int32_t q = pl.vupd[u].p0; q < pl.vupd[u].p0 + pl.vupd[u].np; ++q) src.insert(pl.vpairs[q].src);
+            pl.solve_min_vblocks += (i64)src.size() + 2 * st.nup;
+        }
 }
 
 }  // namespace d3m

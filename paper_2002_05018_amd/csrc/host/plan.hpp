@@ -74,6 +74,8 @@ struct Plan {
     i64 v_tiles_s1 = 0, v_tiles_k = 0;
     std::vector<int64_t> split_map;    // per S1 vector row: global edge if owner, else -1
     std::vector<int64_t> collect_map;  // per global edge: S1 vector row of its owner copy
+    std::vector<int64_t> copy_map;     // per S1 vector row of a non-owner copy of an edge: the owner
+                                       // copy's row, else -1
     std::vector<VDiagTask> vdiag;
     std::vector<VUpdTask> vupd;
     std::vector<VUpdPair> vpairs;
@@ -84,6 +86,11 @@ struct Plan {
     std::vector<int64_t> lm_vrow;      // per global multiplier: its K vector row
     // ---- algorithmic counts -----------------------------------------------
     double flops_s1 = 0.0, flops_s3 = 0.0, flops_update = 0.0;
+    double mfma_flops_update = 0.0;    // update-GEMM work as executed on full 64x64x64 tile
+                                       // products (padding and upper halves of diagonal tiles)
+    std::vector<FactorTile> lhat_s1, lhat_k;  // off-diagonal factor tiles of step 1 / of -K
+    i64 update_min_tiles = 0;          // least tile reads + writes of the update GEMMs, summed over steps
+    i64 solve_min_vblocks = 0;         // least vector-block reads + writes of the solve updates
     double solve_bytes = 0.0;          // complex128 factor bytes read per solve
     i64 factor_entries = 0;
 };

@@ -2,6 +2,7 @@
 // Bunch-Kaufman factorisation of diagonal blocks (pivoting restricted to the
 // block, reference [bunch1977] of the paper), the complex Schur-update GEMM on
 // MFMA, the L-hat = X D^{-1} scaling and the assembly of -K.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -966,6 +967,47 @@ inline unsigned grid_for(int64_t n, int block) {
 }
 }  // namespace
 
+// ------------------------------------------------- growth monitor -------
+// max |L-hat| over the valid entries of factor tiles (one work-group of 256
+// per tile, 16 entries per thread), folded into *gmax as the bit pattern of a
+// non-negative double (NaN compares above every number and is kept).
+template <typename T2>
+__global__ __launch_bounds__(256) void growth_kernel(const FactorTile *tiles, Bases bases, unsigned long long *gmax) {
+    __shared__ double red[4];
+    const FactorTile ft = tiles[blockIdx.x];
+    const T2 *p = enc_ptr<T2>(bases, ft.tile);
+    double m = 0.0;
+    for (int e = threadIdx.x; e < TILE_ELEMS_D; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (r < ft.rows && c < ft.cols) {
+            const double2 z = to_d2(p[e]);
+            const double a = sqrt(z.x * z.x + z.y * z.y);
+            m = (a > m || a != a) ? a : m;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(m, off);
+        m = (o > m || o != o) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+        atomicMax(gmax, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+template <typename T>
+hipError_t launch_growth(const FactorTile *tiles, int64_t ntile, const Bases &b, unsigned long long *gmax,
+                         hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    for (int64_t t0 = 0; t0 < ntile; t0 += (1 << 30)) {
+        const int64_t n = std::min<int64_t>(ntile - t0, 1 << 30);
+        hipLaunchKernelGGL((growth_kernel<T2>), dim3((unsigned)n), dim3(256), 0, s, tiles + t0, b, gmax);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fill_zero(void *p, int64_t n, hipStream_t s) {
     using T2 = typename C2T<T>::type;
@@ -1004,17 +1046,19 @@ size_t bk_lds_bytes(int n, int nthr, bool lds) {
 template <typename T>
 hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const GemmPair *pairs, const Bases &b,
                      const DArrays &D, int *status,
-                     double2 *scratch, hipStream_t s) {
+                     double2 *scratch, hipStream_t s, int variant) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
-    if (maxn <= 64) {
+    if (maxn <= 64 && variant == 0) {
         hipLaunchKernelGGL((bk64_kernel<T2, BK64_NW>), dim3((unsigned)ntask), dim3(64 * BK64_NW), 0, s,
                            tasks, pairs, b, D, status);
         return hipGetLastError();
     }
     int nthr = ((maxn + 63) / 64) * 64;
     if (nthr > 1024) return hipErrorInvalidValue;
-    bool lds = bk_lds_bytes(maxn, nthr, true) <= 160 * 1024 - 256;
+    const bool fits = bk_lds_bytes(maxn, nthr, true) <= 160 * 1024 - 256;
+    if (variant == 1 && !fits) return hipErrorInvalidValue;
+    bool lds = variant == 2 ? false : fits;
     size_t shm = bk_lds_bytes(maxn, nthr, lds);
     if (lds) {
         hipFuncSetAttribute((const void *)bk_kernel<T2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1078,14 +1122,16 @@ hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipSt
     template hipError_t launch_coo_scatter<T>(void *, const int64_t *, const double2 *, int64_t, hipStream_t); \
     template hipError_t launch_bk<T>(const BkTask *, int64_t, int, const GemmPair *, const Bases &,            \
                                      const DArrays &, int *,                                                  \
-                                     double2 *, hipStream_t);                                                 \
+                                     double2 *, hipStream_t, int);                                            \
     template hipError_t launch_gemm<T>(const GemmTask *, int64_t, const GemmPair *, const Bases &, int,        \
                                        hipStream_t);                                                          \
     template hipError_t launch_panel_scale<T>(const GemmTask *, const ScaleTask *, int64_t, const GemmPair *,   \
                                               const Bases &, const DArrays &, int, hipStream_t);              \
     template hipError_t launch_scale<T>(const ScaleTask *, int64_t, const Bases &, const DArrays &,            \
                                         hipStream_t);                                                         \
-    template hipError_t launch_asm<T>(const AsmTask *, int64_t, const Bases &, hipStream_t);
+    template hipError_t launch_asm<T>(const AsmTask *, int64_t, const Bases &, hipStream_t);                    \
+    template hipError_t launch_growth<T>(const FactorTile *, int64_t, const Bases &, unsigned long long *,       \
+                                         hipStream_t);
 D3M_INST(double)
 D3M_INST(float)
 #undef D3M_INST

@@ -24,10 +24,14 @@ template <typename T> hipError_t launch_fill_zero(void *p, int64_t n, hipStream_
 hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_coo_scatter(void *M, const int64_t *off, const double2 *val, int64_t n, hipStream_t s);
+// variant: 0 as the factorisation runs it (register kernel for blocks of at
+// most 64 rows, else the general kernel with the block in LDS when it fits,
+// else in `scratch`); 1 the general kernel with the block in LDS; 2 the
+// general kernel with the block in global scratch (tests of every kernel)
 template <typename T>
 hipError_t launch_bk(const BkTask *tasks, int64_t ntask, int maxn, const GemmPair *pairs, const Bases &b,
                      const DArrays &D, int *status,
-                     double2 *scratch, hipStream_t s);
+                     double2 *scratch, hipStream_t s, int variant = 0);
 size_t bk_lds_bytes(int n, int nthr, bool lds);
 template <typename T>
 hipError_t launch_gemm(const GemmTask *tasks, int64_t ntask, const GemmPair *pairs, const Bases &b, int mode,
@@ -38,6 +42,11 @@ template <typename T>
 hipError_t launch_panel_scale(const GemmTask *tasks, const ScaleTask *stasks, int64_t ntask, const GemmPair *pairs,
                               const Bases &b, const DArrays &D, int rows, hipStream_t s);
 template <typename T> hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipStream_t s);
+// max |entry| over the valid part of the given factor tiles, folded into
+// *gmax (bit pattern of a non-negative double; zeroed by the caller)
+template <typename T>
+hipError_t launch_growth(const FactorTile *tiles, int64_t ntile, const Bases &b, unsigned long long *gmax,
+                         hipStream_t s);
 
 // solve sweeps
 template <typename T>
@@ -59,6 +68,14 @@ hipError_t launch_vscatter_lam(void *X, const void *XK, const int64_t *lmap, int
 template <typename T>
 hipError_t launch_vcollect(double2 *E, const void *X, const int64_t *cmap, int64_t ne, int nrhs, bool accumulate,
                            hipStream_t s);
+
+// largest |difference| between a non-owner subdomain copy of a shared edge
+// (row r of the subdomain vectors X, cmap[r] = its owner's row, else -1) and
+// the owner copy, over all right-hand sides, folded into *dmax (bit pattern of
+// a non-negative double; zeroed by the caller)
+template <typename T>
+hipError_t launch_copy_disc(unsigned long long *dmax, const void *X, const int64_t *cmap, int64_t nrows, int nrhs,
+                            hipStream_t s);
 
 // refinement and adjoint
 // r = f - S E; the largest |r| over the rows of each problem (eprob: problem

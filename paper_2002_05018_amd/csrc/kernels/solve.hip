@@ -2,6 +2,7 @@
 // refinement / adjoint helpers.  Vector tiles hold 64 rows x nrhs columns,
 // column-major (one right-hand side after another), so one 64 x 64 factor
 // tile is applied to many right-hand sides per read.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -627,6 +628,34 @@ __global__ __launch_bounds__(256) void rownorm_max_kernel(unsigned long long *nm
     block_fold_max<1>(nmax, pcur, m, nrhs, c, 1);
 }
 
+// Largest |X(r, c) - X(owner(r), c)| over the subdomain copies r of shared
+// edges that are not the owner copy (copy map: owner row, or -1) and every
+// right-hand side, folded into *dmax (bit pattern of a non-negative double,
+// NaN kept).  One atomic per block.
+template <typename T2>
+__global__ __launch_bounds__(256) void copy_disc_kernel(unsigned long long *dmax, const T2 *X, const int64_t *cmap,
+                                                        int64_t nrows, int nrhs) {
+    __shared__ double red[4];
+    double m = 0.0;
+    const int64_t total = nrows * nrhs;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int c = (int)(idx / nrows);
+        const int64_t r = idx - (int64_t)c * nrows;
+        const int64_t o = cmap[r];
+        if (o < 0) continue;
+        const double2 a = to_d2(X[vrow_elem(r, c, nrhs)]), b = to_d2(X[vrow_elem(o, c, nrhs)]);
+        const double dx = a.x - b.x, dy = a.y - b.y;
+        m = nanmax(m, sqrt(dx * dx + dy * dy));
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) m = nanmax(m, red[w]);
+        atomic_max_bits(dmax, m);
+    }
+}
+
 __global__ void conj_kernel(double2 *out, const double2 *in, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = make_double2(in[i].x, -in[i].y);
@@ -759,6 +788,16 @@ hipError_t launch_rownorm_max(unsigned long long *nmax, const double2 *v, const 
                        eprob, ne, nrhs);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_copy_disc(unsigned long long *dmax, const void *X, const int64_t *cmap, int64_t nrows, int nrhs,
+                            hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    const int64_t total = nrows * nrhs;
+    const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((copy_disc_kernel<T2>), dim3(grid), dim3(256), 0, s, dmax, (const T2 *)X, cmap, nrows, nrhs);
+    return hipGetLastError();
+}
 hipError_t launch_conj(double2 *out, const double2 *in, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(conj_kernel, g1(n), dim3(256), 0, s, out, in, n);
     return hipGetLastError();
@@ -770,6 +809,8 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
 }
 
 #define D3M_INST(T)                                                                                               \
+    template hipError_t launch_copy_disc<T>(unsigned long long *, const void *, const int64_t *, int64_t, int,      \
+                                            hipStream_t);                                                         \
     template hipError_t launch_vsplit<T>(void *, const double2 *, const int64_t *, int64_t, int, int64_t,          \
                                          hipStream_t);                                                            \
     template hipError_t launch_vdiag<T>(const VDiagTask *, int64_t, int, bool, const Bases &, const VBases &,           \

@@ -71,6 +71,13 @@ struct AsmTask {
     int32_t row0[2], col0[2];  // first row / column inside that triangle
 };
 
+// One tile of a factor's off-diagonal block L-hat_ij = X_ij D_jj^{-1}: its
+// valid rows and columns (the growth monitor reads these entries only)
+struct FactorTile {
+    int64_t tile;
+    int32_t rows, cols;
+};
+
 // element offset of tile (a, b), a >= b, inside a packed lower tile triangle
 inline int64_t tri_slot(int64_t a, int64_t b) { return a * (a + 1) / 2 + b; }
 

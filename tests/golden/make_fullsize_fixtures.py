@@ -1,0 +1,105 @@
+"""Writes the oracle's solutions of the full-size workloads at sampled
+unknowns: tests/golden/fullsize_config{2,4,5}.npz and fullsize_config3.npz.
+
+Imports only ``oracle`` and ``workloads``: every stored value is the CPU
+oracle's (the seven steps of Section II in complex128, sparse LU per
+subdomain, Algorithm 1 on K).  Run from the repository root:
+
+    python tests/golden/make_fullsize_fixtures.py 2 4 5 3
+
+Each file holds, for one workload (one problem of the batch for config 3,
+keys prefixed ``p<index>_``):
+  edges      int64 [ns]          sampled global edges (half of them edges
+                                 shared by two or more subdomains)
+  E          complex128 [nrhs, ns] oracle E at those edges
+  E_inf      float64 [nrhs]      max over all edges of |E| per right-hand side
+  lms        int64 [nl]          sampled multipliers (global LM order)
+  lam        complex128 [nrhs, nl] oracle lambda there
+  lam_inf    float64 [nrhs]      max over all multipliers of |lambda|
+  residual   float64 [nrhs]      ||S E - f||_inf / ||f||_inf of the oracle
+                                 solution (oracle S and f)
+  f          complex128 [nrhs, ns] oracle plane-wave load at the sampled edges
+and the oracle's phase timings on the machine that wrote it (seconds).
+
+The right-hand sides are the oracle's plane-wave loads for the workload's
+directions and polarisations (Section II, second line of the BVP).
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle.d3m import D3MOracle, relative_residual  # noqa: E402
+
+SAMPLES = {2: (4096, 2048), 4: (2048, 1024), 5: (4096, 2048), 3: (256, 128)}
+
+
+def _sample(rng, o, n_edge, n_lm):
+    dec = o.dec
+    mult = np.array([len(s) for s in dec.sub_of_edge])
+    shared = np.nonzero(mult >= 2)[0]
+    single = np.nonzero(mult < 2)[0]
+    h = min(n_edge // 2, shared.size)
+    e = np.concatenate([rng.choice(shared, h, replace=False),
+                        rng.choice(single, min(n_edge - h, single.size), replace=False)])
+    lm = rng.choice(dec.n_lm, min(n_lm, dec.n_lm), replace=False) if dec.n_lm else np.zeros(0, np.int64)
+    return np.sort(e).astype(np.int64), np.sort(lm).astype(np.int64)
+
+
+def solve_problem(prob, seed, n_edge, n_lm, log):
+    t0 = time.perf_counter()
+    o = D3MOracle.from_problem(prob)
+    t1 = time.perf_counter()
+    log(f"  setup {t1 - t0:.1f} s ({o.fem.topo.n_edges} edges, {o.dec.N} subdomains, {o.dec.n_lm} LMs)")
+    o.factor()
+    t2 = time.perf_counter()
+    log(f"  factor {t2 - t1:.1f} s {o.timings}")
+    f = o.fem.planewave_rhs(prob.dirs, prob.pols)
+    E = o.solve(f)
+    t3 = time.perf_counter()
+    log(f"  solve {t3 - t2:.1f} s")
+    r = np.abs((o.fem.S @ E.T).T - f).max(axis=1) / np.abs(f).max(axis=1)
+    assert float(r.max()) == relative_residual(o.fem.S, E, f)
+    log(f"  residual {r.max():.2e}")
+    rng = np.random.default_rng(seed)
+    e, lm = _sample(rng, o, n_edge, n_lm)
+    tim = {k: float(v) for k, v in o.timings.items()}
+    out = {"edges": e, "E": E[:, e], "E_inf": np.abs(E).max(axis=1), "lms": lm,
+           "lam": o.lam[:, lm], "lam_inf": np.abs(o.lam).max(axis=1) if o.lam.size else np.zeros(E.shape[0]),
+           "residual": r, "f": f[:, e],
+           "timing_names": np.array(sorted(tim)), "timing_s": np.array([tim[k] for k in sorted(tim)])}
+    return out
+
+
+def main(cfgs):
+    def log(m):
+        print(m, flush=True)
+
+    for cfg in cfgs:
+        n_edge, n_lm = SAMPLES[cfg]
+        path = os.path.join(HERE, f"fullsize_config{cfg}.npz")
+        log(f"config {cfg} -> {path}")
+        if cfg == 3:
+            probs = W.make_batch_config()
+            data = {}
+            for p, prob in enumerate(probs):
+                log(f" problem {p}: {prob.n}^3 hexes, boxes {prob.parts}")
+                out = solve_problem(prob, 3000 + p, n_edge, n_lm, log)
+                for k, v in out.items():
+                    data[f"p{p}_{k}"] = v
+            data["count"] = np.array(len(probs))
+        else:
+            data = solve_problem(W.make_config(cfg), 1000 + cfg, n_edge, n_lm, log)
+        np.savez_compressed(path, **data)
+
+
+if __name__ == "__main__":
+    main([int(a) for a in sys.argv[1:]] or [2, 4, 5, 3])

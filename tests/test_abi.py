@@ -67,3 +67,47 @@ def test_query_counts():
     assert q["n_edges"] == 1854 and q["n_lm"] == 246 and q["n_blocks"] == 4
     assert q["n_subdomains"] == 4 and q["max_block"] == 63
     assert q["flops_domain"] > 0 and q["flops_block_ldlt"] > 0
+
+
+def test_debug_bk_rejects_bad_arguments_on_the_host():
+    """The Bunch-Kaufman test hook validates its arguments before any HIP
+    call; without a device a valid call reports D3M_ENODEV."""
+    from paper_2002_05018_amd import D3MError
+    from paper_2002_05018_amd._lib import debug_bk
+    a = np.eye(4, dtype=np.complex128)[None]
+    with pytest.raises(D3MError, match="EINVAL"):
+        debug_bk(a, variant=3)
+    with pytest.raises(D3MError, match="EINVAL"):
+        debug_bk(a, precision=7)
+    with pytest.raises(D3MError, match="EINVAL"):
+        debug_bk(np.eye(300, dtype=np.complex128)[None], variant=1)  # 300 rows do not fit in LDS
+    with pytest.raises(ValueError):
+        debug_bk(np.zeros((2, 3, 4)))
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(D3MError, match="ENODEV"):
+            debug_bk(a)
+
+
+def test_binding_rejects_mismatched_buffers_on_the_host():
+    """solve/adjoint check caller buffers before handing pointers to the
+    library (a wrong shape, dtype, layout or device would be an out-of-bounds
+    access there); eps_r must have one value per tetrahedron."""
+    import torch
+    prob = W.make_problem(2, (2, 1, 1))
+    s = _setup(prob)
+    n = s.n_edges
+    f = torch.zeros((2, n), dtype=torch.complex128)
+    bad_outs = [torch.zeros((2, n + 1), dtype=torch.complex128), torch.zeros((2, n), dtype=torch.complex64),
+                torch.zeros((n, 2), dtype=torch.complex128).t(), torch.zeros((3, n), dtype=torch.complex128)]
+    for out in bad_outs:
+        with pytest.raises(ValueError):
+            s.solve(f, out=out)
+    with pytest.raises(ValueError):
+        s.adjoint(torch.zeros((2, n), dtype=torch.complex64), f)
+    with pytest.raises(ValueError):
+        s.adjoint(f, torch.zeros((1, n), dtype=torch.complex128))
+    with pytest.raises(ValueError):
+        s.adjoint(f, f.numpy())
+    with pytest.raises(ValueError):
+        s.update_eps(np.ones(prob.tets.shape[0] + 1))

@@ -16,13 +16,10 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import assert_rhs_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 _cache = {}
@@ -52,7 +49,7 @@ def test_batch_fp64_matches_oracle_per_problem():
     E = E.cpu().numpy()
     assert info["residual"] <= 1e-11
     for p in range(len(probs)):
-        assert _rel(E[:, eo[p]:eo[p + 1]], ref[p]) <= 1e-10, p
+        assert_rhs_close(E[:, eo[p]:eo[p + 1]], ref[p], 1e-10, f"problem {p}")
 
 
 def test_batch_fp32_refinement_per_problem():
@@ -62,7 +59,7 @@ def test_batch_fp32_refinement_per_problem():
     assert info["converged"] and info["residual"] <= 1e-10
     E = E.cpu().numpy()
     for p in range(len(probs)):
-        assert _rel(E[:, eo[p]:eo[p + 1]], ref[p]) <= 1e-9, p
+        assert_rhs_close(E[:, eo[p]:eo[p + 1]], ref[p], 1e-9, f"problem {p}")
 
 
 def test_batch_scaled_problem_alone_differs_only_by_scale():
@@ -80,7 +77,7 @@ def test_batch_scaled_problem_alone_differs_only_by_scale():
     u.factor("fp64")
     fp = np.ascontiguousarray(f[:, eo[0]:eo[1]])
     Eu = u.solve(torch.from_numpy(fp).cuda()).cpu().numpy()
-    assert _rel(Eu, ref[0] / sc) <= 1e-10
+    assert_rhs_close(Eu, ref[0] / sc, 1e-10, "unit cube")
 
 
 def test_graph_replays_match_eager_bitwise():
@@ -124,7 +121,7 @@ def test_tuning_variants_agree(tune):
     s.factor("fp64")
     got, info = s.solve(f, with_info=True)
     assert info["residual"] <= 1e-11
-    assert _rel(got.cpu().numpy(), want) <= 1e-12
+    assert_rhs_close(got.cpu().numpy(), want, 1e-12, str(tune))
 
 
 def test_autotune_picks_a_valid_tuning():
@@ -138,7 +135,7 @@ def test_autotune_picks_a_valid_tuning():
     assert not res["cached"] and len(res["trials"]) == 18
     assert s.tuning() == res["tuning"]
     s.factor("fp64")
-    assert _rel(s.solve(f).cpu().numpy(), want) <= 1e-12
+    assert_rhs_close(s.solve(f).cpu().numpy(), want, 1e-12, "autotuned")
 
 
 def test_batch_residual_is_per_problem():

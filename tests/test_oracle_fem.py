@@ -145,3 +145,28 @@ def test_whitney_interpolation_of_constants():
             u = c @ (x[j] - x[i])
             val += u * (lam[i] * G[t, j] - lam[j] * G[t, i])
         assert np.allclose(val, c, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_probe_matrix_reproduces_rotational_linear_fields(n):
+    """The lowest-order edge-element space holds every field a + b x r exactly
+    (its curl 2b is constant and its divergence zero), so the edge degrees of
+    freedom u_e = int_e F . dl (for a linear F, the midpoint value dotted with
+    the edge vector) probed anywhere in the mesh give F itself.  Pins the
+    point location, the barycentrics and the basis of probe_matrix: a wrong
+    tetrahedron, sign or gradient changes the value."""
+    xyz, tets = W.kuhn_cube_mesh(n)
+    topo = fem.Topology(xyz, tets)
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(3)
+    b = rng.standard_normal(3)
+    lo, hi = topo.xyz[topo.edges[:, 0]], topo.xyz[topo.edges[:, 1]]
+    mid = 0.5 * (lo + hi)
+    u = np.einsum("ex,ex->e", a + np.cross(b, mid), hi - lo)
+    pts = np.concatenate([rng.random((40, 3)),
+                          xyz[rng.choice(len(xyz), 4, replace=False)],       # vertices
+                          0.5 * (lo[:3] + hi[:3])])                             # edge midpoints
+    P = fem.probe_matrix(topo, pts)
+    got = P @ u
+    want = a[None, :] + np.cross(b[None, :], pts)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
