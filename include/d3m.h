@@ -253,6 +253,24 @@ int d3m_factor_growth(d3m_handle h, double *lhat_subdomains, double *lhat_k);
 int d3m_solve(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E,
               d3m_solve_info *info, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the FP64 solve
+ * of d3m_solve (steps 6-7) with its working vectors in a fixed device array
+ * of D3M_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends.  Only kernel launches are enqueued on `stream`
+ * (no allocation, no memset, no host synchronisation); the call returns
+ * without waiting for them.
+ *   rhs, E  [nrhs][n_edges] complex128 device buffers (caller-owned).
+ * The handle must hold FP64 factors.  The scratch of one GPU is shared by all
+ * handles and calls on it: calls whose kernels overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Errors: D3M_EINVAL (null or host buffers, nrhs < 1, or a scratch need above
+ * D3M_NOALLOC_SCRATCH_BYTES: the message gives the need), D3M_ESTATE (not
+ * factored in FP64, host-only handle), D3M_EHIP. */
+#define D3M_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int d3m_solve_noalloc(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E,
+                      void *stream);
+
 /* Adjoint of E = S(eps_r)^{-1} f with respect to eps_r, reusing the factors
  * (S is complex symmetric, so S^{-T} = S^{-1}):
  *   w = S^{-1} conj(grad_E),  grad_eps[t] = k^2 Re sum_rhs w_t^T M_t E_t,

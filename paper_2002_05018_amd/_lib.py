@@ -41,7 +41,8 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
-                    "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth"]
+                    "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth",
+                    "d3m_solve_noalloc"]
 
 
 class d3m_c128(C.Structure):
@@ -125,6 +126,8 @@ _lib.d3m_debug_bk.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_int
 _lib.d3m_debug_bk.restype = C.c_int
 _lib.d3m_factor_growth.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 _lib.d3m_factor_growth.restype = C.c_int
+_lib.d3m_solve_noalloc.argtypes = [_h, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+_lib.d3m_solve_noalloc.restype = C.c_int
 for _f in ("d3m_setup", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch", "d3m_update_eps",
            "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
            "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"):
@@ -316,6 +319,19 @@ class Solver:
         if with_info:
             return out, {"iterations": info.iterations, "converged": bool(info.converged),
                          "residual": info.residual, "copy_discrepancy": info.copy_discrepancy}
+        return out
+
+    def solve_noalloc(self, rhs, out, stream=None):
+        """d3m_solve_noalloc: FP64 solve into a caller tensor, with the
+        library's fixed device scratch (rhs and out: contiguous complex128
+        CUDA tensors [nrhs, n_edges]).  Enqueues kernels only; no wait."""
+        import torch
+        if not isinstance(rhs, torch.Tensor) or rhs.dtype != torch.complex128 or rhs.dim() != 2 \
+                or rhs.shape[1] != self.n_edges or not rhs.is_cuda or not rhs.is_contiguous():
+            raise ValueError("rhs must be a contiguous complex128 CUDA tensor [nrhs, n_edges]")
+        _check_like(out, rhs, "out")
+        _check(_lib.d3m_solve_noalloc(self._handle, C.c_void_p(rhs.data_ptr()), rhs.shape[0],
+                                      C.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
     def adjoint(self, grad_E, E, want_w=False, stream=None):

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libd3m.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels/factor.hip", "kernels/solve.hip"]
+HIP_SOURCES = ["kernels/factor.hip", "kernels/solve.hip", "solve_noalloc.hip"]
 CXX_SOURCES = ["host/mesh.cpp", "host/decomp.cpp", "host/plan.cpp", "d3m_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-variable", "-Wno-unused-result"]

@@ -16,6 +16,7 @@
 #include "host/plan.hpp"
 #include "host/problem.hpp"
 #include "kernels/launch.hpp"
+#include "noalloc.hpp"
 
 using namespace d3m;
 
@@ -129,6 +130,7 @@ struct d3m_problem {
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;
     bool capturing = false;
+    bool quiet = false;  // no profiling events (the allocation-free solve)
     static void destroy_graph(Graph &g) {
         if (g.x) (void)hipGraphExecDestroy(g.x);
         if (g.g) (void)hipGraphDestroy(g.g);
@@ -206,7 +208,7 @@ struct d3m_problem {
     // ---- profiling helpers
     // opt.profile: 0 off, 1 the update GEMMs only, 2 every kernel group
     bool prof_wanted(int kid) const {
-        if (capturing) return false;  // graphs carry no timing events
+        if (capturing || quiet) return false;  // graphs carry no timing events
         return opt.profile >= 2 || (opt.profile == 1 && kid == KID_UPDATE);
     }
     void prof_begin(int kid, hipEvent_t &a, hipStream_t s) {
@@ -597,11 +599,11 @@ int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases
 // E (=|+=) S^{-1} f through the factors of precision T; f and E on the
 // device; every launch of recipe steps 6-7, in order, on s
 template <typename T>
-int solve_launch(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
+int solve_launch_vb(d3m_problem *h, const VBases &vb, const double2 *f, double2 *E, int nrhs, bool accumulate,
+                    hipStream_t s) {
     int rc;
     const Plan &pl = h->pl;
     Bases b = bases_of<T>(h);
-    VBases vb = vbases_of<T>(h);
     hipEvent_t ev{};
     h->prof_begin(KID_SOLVE, ev, s);
     HIPCHK(launch_vsplit<T>(vb.p[V_X], f, h->d_split, pl.v_tiles_s1 * 64, nrhs, h->mesh.ne, s));
@@ -615,6 +617,20 @@ int solve_launch(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool ac
     HIPCHK(launch_vcollect<T>(E, vb.p[V_X], h->d_collect, h->mesh.ne, nrhs, accumulate, s));
     h->prof_end(KID_SOLVE, ev, 0.0, s);
     return D3M_OK;
+}
+
+template <typename T>
+int solve_launch(d3m_problem *h, const double2 *f, double2 *E, int nrhs, bool accumulate, hipStream_t s) {
+    return solve_launch_vb<T>(h, vbases_of<T>(h), f, E, nrhs, accumulate, s);
+}
+
+// bytes of solve vector array v (precision T) for nrhs right-hand sides,
+// rounded up to 256
+template <typename T>
+size_t vec_bytes(const d3m_problem *h, int v, int nrhs) {
+    const i64 tiles = v < V_KX ? h->pl.v_tiles_s1 : h->pl.v_tiles_k;
+    const size_t b = (size_t)std::max<i64>(tiles, 1) * 64 * nrhs * sizeof(T) * 2;
+    return (b + 255) & ~(size_t)255;
 }
 
 template <typename T>
@@ -780,6 +796,41 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
 }
 
 }  // namespace
+
+namespace d3m {
+
+int set_error(int code, const char *msg) { return fail(code, msg); }
+
+int handle_device(const d3m_problem *h) { return h->opt.device; }
+
+int solve_scratch_bytes(const d3m_problem *h, int nrhs, size_t *bytes) {
+    if (!h->device_ready) return fail(D3M_ESTATE, "handle was set up host-only");
+    if (h->factored != 1) return fail(D3M_ESTATE, "the allocation-free solve needs FP64 factors (d3m_factor D3M_FP64)");
+    size_t need = 0;
+    for (int v = 0; v < VARR_COUNT; ++v) need += vec_bytes<double>(h, v, nrhs);
+    *bytes = need;
+    return D3M_OK;
+}
+
+int solve_into_scratch(d3m_problem *h, const double2 *f, double2 *E, int nrhs, void *scratch, size_t bytes,
+                       hipStream_t s) {
+    size_t need = 0;
+    int rc = solve_scratch_bytes(h, nrhs, &need);
+    if (rc != D3M_OK) return rc;
+    if (need > bytes) return fail(D3M_EINVAL, "scratch too small");
+    VBases vb;
+    char *p = static_cast<char *>(scratch);
+    for (int v = 0; v < VARR_COUNT; ++v) {
+        vb.p[v] = p;
+        p += vec_bytes<double>(h, v, nrhs);
+    }
+    h->quiet = true;
+    rc = solve_launch_vb<double>(h, vb, f, E, nrhs, false, s);
+    h->quiet = false;
+    return rc;
+}
+
+}  // namespace d3m
 
 namespace {
 
