@@ -337,7 +337,19 @@ typedef struct {
                                 (default) or 16 (four work-groups per tile,
                                 so a short block column's panel products
                                 run on four times as many compute units)    */
-    int32_t reserved[1];
+    int32_t solve_seq;       /* 1: each subdomain sweep of the solve (steps 6
+                                and 7 over the factors of step 1) is one
+                                launch in which a work-group runs one
+                                subdomain's tile columns in order, every
+                                target gathering all its products at once;
+                                0 (default): one launch per tile column over
+                                all subdomains                               */
+    int32_t solve_narrow;    /* sweep steps with fewer update tasks than this
+                                take 16 right-hand sides per work-group
+                                whatever solve_cols says (more, shorter
+                                work-groups where a step is latency-bound);
+                                0 (default): never                           */
+    int32_t reserved[3];
 } d3m_tuning;
 
 /* Read / replace the tuning.  A new s1_block, k_block or k_fuse rebuilds the factor schedule

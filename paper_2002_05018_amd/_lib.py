@@ -80,7 +80,8 @@ class d3m_batch_item(C.Structure):
 class d3m_tuning(C.Structure):
     _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
                 ("k_block", C.c_int32), ("side_early", C.c_int32), ("k_fuse", C.c_int32),
-                ("panel_rows", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("panel_rows", C.c_int32), ("solve_seq", C.c_int32), ("solve_narrow", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class d3m_bk_out(C.Structure):
@@ -407,7 +408,8 @@ class Solver:
         """Replay captured HIP graphs (True) or launch eagerly (False) from now on."""
         _check(_lib.d3m_set_graphs(self._handle, int(bool(use_graph))))
 
-    TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early", "k_fuse", "panel_rows")
+    TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early", "k_fuse", "panel_rows",
+                   "solve_seq", "solve_narrow")
 
     def tuning(self):
         t = d3m_tuning()

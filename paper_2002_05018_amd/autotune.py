@@ -20,7 +20,12 @@ the solve.  The candidates are the launch shapes the schedules expose:
 * ``panel_rows``: rows of a panel tile per work-group (64, or 16 with four
   work-groups per tile);
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
-  (16 or 32 columns of the MFMA tile).
+  (16 or 32 columns of the MFMA tile);
+* ``solve_seq``: the subdomain sweeps of the solve as one launch per
+  direction (a work-group per subdomain runs its tile columns in order) or
+  one launch per tile column;
+* ``solve_narrow``: below how many update tasks a sweep step takes 16
+  right-hand sides per work-group (more, shorter work-groups).
 
 The search is coordinate-wise in the order of ``space``: each parameter is
 timed over its values with the others held at their current best, then
@@ -41,6 +46,8 @@ DEFAULT_SPACE = {
     "side_early": (0, 1),
     "k_fuse": (0, 1),
     "panel_rows": (64, 16),
+    "solve_seq": (0, 1),
+    "solve_narrow": (0, 1024, 4096),
     "solve_cols": (32, 16),
 }
 _PREC = {0: "fp64", 1: "fp32_ir", "fp64": "fp64", "fp32_ir": "fp32_ir"}
@@ -86,8 +93,9 @@ def autotune(solver, rhs, precision="fp64", space=None, repeats=2, cache=None, l
     import torch
     space = dict(DEFAULT_SPACE if space is None else space)
     nrhs = int(rhs.shape[0])
-    if nrhs <= 16:
-        space.pop("solve_cols", None)  # one column block covers every right-hand side
+    if nrhs <= 16:  # one column block covers every right-hand side
+        space.pop("solve_cols", None)
+        space.pop("solve_narrow", None)
     key = signature(solver, nrhs, precision)
     store = {}
     if cache and os.path.exists(cache):

@@ -79,6 +79,7 @@ struct d3m_problem {
     double2 *d_coo_val = nullptr;
     int64_t *d_split = nullptr, *d_collect = nullptr, *d_hmap = nullptr, *d_lmap = nullptr;
     int64_t *d_copymap = nullptr;
+    int64_t *d_sq_fwd = nullptr, *d_sq_bwd = nullptr;
     unsigned long long *d_disc = nullptr;
     FactorTile *d_lhat_s1 = nullptr, *d_lhat_k = nullptr;
     unsigned long long *d_growth = nullptr;
@@ -299,6 +300,8 @@ int upload_schedules(d3m_problem *h, bool replace) {
     UPS(h->d_split, pl.split_map);
     UPS(h->d_collect, pl.collect_map);
     UPS(h->d_copymap, pl.copy_map);
+    UPS(h->d_sq_fwd, pl.sq_fwd_off);
+    UPS(h->d_sq_bwd, pl.sq_bwd_off);
     UPS(h->d_lhat_s1, pl.lhat_s1);
     UPS(h->d_lhat_k, pl.lhat_k);
     UPS(h->d_hmap, pl.h_map);
@@ -586,13 +589,16 @@ int factor_impl(d3m_problem *h, hipStream_t s) {
 template <typename T>
 int solve_step(d3m_problem *h, const SolveStep &st, const Bases &b, const VBases &vb, bool bwd, int nrhs,
                hipStream_t s) {
+    // steps with few update tasks take 16 right-hand sides per work-group
+    // (twice the work-groups, half the MFMA chain each)
+    const int cols = st.nup < h->tune.solve_narrow ? 16 : h->tune.solve_cols;
     if (st.up_first)
         HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
-                              vb, h->D, nrhs, h->tune.solve_cols, s));
-    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, h->tune.solve_cols, s));
+                              vb, h->D, nrhs, cols, s));
+    HIPCHK(launch_vdiag<T>(h->d_vdiag + st.dg0, st.ndg, st.dg_maxt, bwd, b, vb, h->D, nrhs, cols, s));
     if (!st.up_first)
         HIPCHK(launch_vupd<T>(h->d_vupd + st.up0, h->d_vfuse + st.up0, st.nup, h->d_vpairs, h->d_vdiag, st.up_mode, b,
-                              vb, h->D, nrhs, h->tune.solve_cols, s));
+                              vb, h->D, nrhs, cols, s));
     return D3M_OK;
 }
 
@@ -607,13 +613,21 @@ int solve_launch_vb(d3m_problem *h, const VBases &vb, const double2 *f, double2 
     hipEvent_t ev{};
     h->prof_begin(KID_SOLVE, ev, s);
     HIPCHK(launch_vsplit<T>(vb.p[V_X], f, h->d_split, pl.v_tiles_s1 * 64, nrhs, h->mesh.ne, s));
-    for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
+    if (h->tune.solve_seq)
+        HIPCHK(launch_vseq<T>(h->d_vupd, h->d_vfuse, h->d_sq_fwd, h->dc.N, h->d_vpairs, h->d_vdiag, false, b, vb, h->D,
+                              nrhs, h->tune.solve_cols, s));
+    else
+        for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
     HIPCHK(launch_vgather_h<T>(vb.p[V_KX], vb.p[V_X], h->d_hmap, pl.v_tiles_k * 64, nrhs, s));
     for (const auto &st : pl.k_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
     HIPCHK(launch_fill_zero<T>(vb.p[V_KACC], pl.v_tiles_k * 64 * nrhs, s));
     for (const auto &st : pl.k_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
     HIPCHK(launch_vscatter_lam<T>(vb.p[V_X], vb.p[V_KX], h->d_lmap, pl.v_tiles_s1 * 64, nrhs, s));
-    for (const auto &st : pl.s1_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
+    if (h->tune.solve_seq)
+        HIPCHK(launch_vseq<T>(h->d_vupd, h->d_vfuse, h->d_sq_bwd, h->dc.N, h->d_vpairs, h->d_vdiag, true, b, vb, h->D,
+                              nrhs, h->tune.solve_cols, s));
+    else
+        for (const auto &st : pl.s1_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
     HIPCHK(launch_vcollect<T>(E, vb.p[V_X], h->d_collect, h->mesh.ne, nrhs, accumulate, s));
     h->prof_end(KID_SOLVE, ev, 0.0, s);
     return D3M_OK;
@@ -996,6 +1010,8 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     if (t->k_fuse != 0 && t->k_fuse != 1) return fail(D3M_EINVAL, "k_fuse must be 0 or 1");
     if (t->panel_rows != 0 && t->panel_rows != 16 && t->panel_rows != 64)
         return fail(D3M_EINVAL, "panel_rows must be 0, 16 or 64");
+    if (t->solve_seq != 0 && t->solve_seq != 1) return fail(D3M_EINVAL, "solve_seq must be 0 or 1");
+    if (t->solve_narrow < 0) return fail(D3M_EINVAL, "solve_narrow must be >= 0");
     const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block, old_f = h->tune.k_fuse;
     h->drop_graphs();
     h->tune = *t;

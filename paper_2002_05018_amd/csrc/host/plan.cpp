@@ -767,6 +767,60 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     fuse_sweep(pl.k_fwd, false);
     fuse_sweep(pl.k_bwd, true);
     fuse_sweep(pl.s1_bwd, true);
+
+    // -------------------- S1 sweeps as one ordered task list per subdomain --
+    // (tuning solve_seq) Left-looking: each target tile of a subdomain is
+    // written by one task that gathers every product it needs, so one
+    // work-group can run a subdomain's whole sweep in order with no
+    // read-modify-write of partial sums.  Forward: x_j -= sum_{c<j} L(j,c) y_c
+    // fused with y_j = TT_j x_j, v_j = D_j^{-1} y_j, for the tile columns in
+    // order, then the multiplier rows a: x_a -= sum_c L(a,c) y_c.  Backward:
+    // for j from the last column down, acc_j = sum_{a>j} L(a,j)^T x_a fused
+    // with x_j = TT_j^T (v_j - acc_j) (x_a of the multiplier rows is lambda).
+    pl.sq_fwd_off.assign(N + 1, 0);
+    pl.sq_bwd_off.assign(N + 1, 0);
+    auto s1_diag = [&](int d, int j, bool bwd) {
+        VDiagTask t{};
+        t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+        t.x = V(V_X, pl.vs1[d] + j);
+        t.y = bwd ? -1 : V(V_Y, pl.vs1[d] + j);
+        t.v = V(V_V, pl.vs1[d] + j);
+        t.acc = bwd ? V(V_ACC, pl.vs1[d] + j) : -1;
+        t.drow = pl.drow_s1[d] + (i64)j * TILE;
+        t.t = 1;
+        t.n = mrows(d, j);
+        pl.vdiag.push_back(t);
+        return (i64)pl.vdiag.size() - 1;
+    };
+    for (int d = 0; d < N; ++d) {
+        pl.sq_fwd_off[d] = (i64)pl.vupd.size();
+        for (int a = 0; a < pl.T[d]; ++a) {
+            VUpdTask u{V(V_X, pl.vs1[d] + a), (int32_t)pl.vpairs.size(), 0};
+            for (int c = 0; c < std::min(a, pl.TE[d]); ++c)
+                if (nz[d][a][c]) {
+                    pl.vpairs.push_back({E(ARR_M, mslot(d, a, c)), V(V_Y, pl.vs1[d] + c)});
+                    ++u.np;
+                }
+            pl.vupd.push_back(u);
+            pl.vfuse.push_back(a < pl.TE[d] ? s1_diag(d, a, false) : -1);
+        }
+    }
+    pl.sq_fwd_off[N] = (i64)pl.vupd.size();
+    for (int d = 0; d < N; ++d) {
+        pl.sq_bwd_off[d] = (i64)pl.vupd.size();
+        for (int j = pl.TE[d] - 1; j >= 0; --j) {
+            VUpdTask u{V(V_ACC, pl.vs1[d] + j), (int32_t)pl.vpairs.size(), 0};
+            for (int a = j + 1; a < pl.T[d]; ++a)
+                if (nz[d][a][j]) {
+                    pl.vpairs.push_back({E(ARR_M, mslot(d, a, j)), V(V_X, pl.vs1[d] + a)});
+                    ++u.np;
+                }
+            pl.vupd.push_back(u);
+            pl.vfuse.push_back(s1_diag(d, j, true));
+        }
+    }
+    pl.sq_bwd_off[N] = (i64)pl.vupd.size();
+    if (pl.vfuse.size() != pl.vupd.size()) throw Error{-1, "internal: fused-solve index list out of step"};
     for (VUpdTask &u : pl.vupd)
         if (u.np > 0) { u.l0 = pl.vpairs[u.p0].l; u.src0 = pl.vpairs[u.p0].src; }
 

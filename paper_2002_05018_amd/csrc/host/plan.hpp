@@ -81,6 +81,11 @@ struct Plan {
     std::vector<VUpdPair> vpairs;
     std::vector<int64_t> vfuse;  // per update task: diagonal solve it completes (index into vdiag) or -1
     std::vector<SolveStep> s1_fwd, k_fwd, k_bwd, s1_bwd;
+    // the S1 sweeps as ordered per-subdomain task lists (left-looking, each
+    // target written once): subdomain d's forward tasks are vupd
+    // [sq_fwd_off[d], sq_fwd_off[d+1]) in mode 0, its backward tasks
+    // [sq_bwd_off[d], sq_bwd_off[d+1]) in mode 1, diagonal solves fused (vfuse)
+    std::vector<i64> sq_fwd_off, sq_bwd_off;
     std::vector<int64_t> h_map;        // per K vector row: the two subdomain vector rows (-1: padding)
     std::vector<int64_t> lam_map;      // per S1 vector row: K vector row of a multiplier row, else -1
     std::vector<int64_t> lm_vrow;      // per global multiplier: its K vector row

@@ -60,6 +60,12 @@ template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                        const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
                        int cols, hipStream_t s);
+// a whole S1 sweep, one work-group per subdomain (and column block) running
+// its ordered task list [off[d], off[d + 1]) (forward: mode 0, backward: mode 1)
+template <typename T>
+hipError_t launch_vseq(const VUpdTask *tasks, const int64_t *fuse, const int64_t *off, int nsub,
+                       const VUpdPair *pairs, const VDiagTask *vdiag, bool bwd, const Bases &b, const VBases &vb,
+                       const DArrays &D, int nrhs, int cols, hipStream_t s);
 template <typename T>
 hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s);
 template <typename T>

@@ -329,29 +329,46 @@ __global__ __launch_bounds__(256) void vdiag_multi_kernel(const VDiagTask *tasks
 // the diagonal solve fuse[task] (forward: the target is that block's x;
 // backward: its accumulator), so the work-group goes on with that solve from
 // the new values kept in LDS, saving a launch per sweep step.
+// lane `l`'s value of a 64-bit register, wave-uniform
+__device__ __forceinline__ int64_t rdlane64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+// One update task (and its fused diagonal solve) for the right-hand sides
+// c0 .. c0 + ncol - 1, by the whole work-group.
 template <typename T, int MODE, int NCB>
-__global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask,
-                                                   const VUpdPair *pairs, const VDiagTask *vdiag, Bases b, VBases vb,
-                                                   DArrays D, int nrhs) {
+__device__ __forceinline__ void vupd_task(const VUpdTask &tk, int64_t fz, const VUpdPair *pairs,
+                                          const VDiagTask *vdiag, const Bases &b, const VBases &vb, const DArrays &D,
+                                          int nrhs, int c0, int ncol, SvSmem<typename C2T<T>::type, NCB> &sm) {
     using M = Mfma<T>;
     using T2 = typename C2T<T>::type;
     constexpr bool TR = MODE != 0;
-    __shared__ SvSmem<T2, NCB> sm;
-    const int64_t task = xcd_task(ntask);
-    if (task >= ntask) return;
-    const VUpdTask tk = tasks[task];
-    const int64_t fz = fuse[task];
-    const int c0 = blockIdx.y * 16 * NCB;
-    const int ncol = min(16 * NCB, nrhs - c0);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int m = 16 * (threadIdx.x >> 6) + li;
     SvAcc<T, NCB> acc;
     acc.zero();
-    VDiagTask dg{};
-    if (fz >= 0) dg = vdiag[fz];
     // lf holds the fragment of the next product; after the last one it takes
     // the fused diagonal solve's TT, whose loads then overlap the last product
     T2 lf[16], xr[4 * NCB];
+    // the first product's operands come from the task itself: their loads go
+    // out before anything that waits on another load
+    if (tk.np > 0) {
+        sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, tk.l0));
+        sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.src0, nrhs), nullptr, c0, ncol);
+    }
+    // the task's pair list, 64 pairs at a time, one per lane: the addresses of
+    // product p + 1 are read from a register (readlane), not loaded while
+    // product p waits
+    int64_t pl_l = 0, pl_s = 0;
+    if (tk.np > 1 && lane < tk.np) {
+        const VUpdPair pr = pairs[tk.p0 + lane];
+        pl_l = pr.l;
+        pl_s = pr.src;
+    }
+    VDiagTask dg{};
+    if (fz >= 0) dg = vdiag[fz];
     T2 *out = vptr<T2>(vb, tk.out, nrhs) + (int64_t)c0 * 64;
     const T2 *vin = nullptr;
     if (fz >= 0 && TR) vin = vptr<T2>(vb, dg.v, nrhs) + (int64_t)c0 * 64;
@@ -368,13 +385,7 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
             opre[cb][r] = kPre && MODE != 1 && c < ncol ? out[c * 64 + m] : T2{0, 0};
             vpre[cb][r] = kPre && vin && c < ncol ? vin[c * 64 + m] : T2{0, 0};
         }
-    if (tk.np > 0) {
-        const VUpdPair pr{tk.l0, tk.src0};
-        sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
-        sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
-    } else if (fz >= 0) {
-        sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
-    }
+    if (tk.np == 0 && fz >= 0) sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
     for (int p = 0; p < tk.np; ++p) {
         T2 *xs = sm.xs[p & 1];
         sv_put_x<T2, NCB>(xs, xr);
@@ -383,9 +394,18 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
 #pragma unroll
         for (int j = 0; j < 16; ++j) lc[j] = lf[j];
         if (p + 1 < tk.np) {
-            const VUpdPair pr = pairs[tk.p0 + p + 1];
-            sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, pr.l));
-            sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, pr.src, nrhs), nullptr, c0, ncol);
+            const int q = p + 1;
+            if ((q & 63) == 0) {  // next 64 pairs of the list
+                const int i = q + lane;
+                if (i < tk.np) {
+                    const VUpdPair pr = pairs[tk.p0 + i];
+                    pl_l = pr.l;
+                    pl_s = pr.src;
+                }
+            }
+            const int64_t nl = rdlane64(pl_l, q & 63), ns = rdlane64(pl_s, q & 63);
+            sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, nl));
+            sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, ns, nrhs), nullptr, c0, ncol);
         } else if (fz >= 0) {
             sv_load_l<T2, TR>(lf, enc_ptr<T2>(b, dg.tt));
         }
@@ -414,6 +434,41 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
     if (fz < 0) return;
     __syncthreads();
     sv_diag<T, TR, NCB>(lf, dg, c0, ncol, vb, D, nrhs, xd, sm.xs[(tk.np + 1) & 1]);
+}
+
+template <typename T, int MODE, int NCB>
+__global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask,
+                                                   const VUpdPair *pairs, const VDiagTask *vdiag, Bases b, VBases vb,
+                                                   DArrays D, int nrhs) {
+    using T2 = typename C2T<T>::type;
+    __shared__ SvSmem<T2, NCB> sm;
+    const int64_t task = xcd_task(ntask);
+    if (task >= ntask) return;
+    const int c0 = blockIdx.y * 16 * NCB;
+    vupd_task<T, MODE, NCB>(tasks[task], fuse[task], pairs, vdiag, b, vb, D, nrhs, c0, min(16 * NCB, nrhs - c0), sm);
+}
+
+// A whole S1 sweep: work-group g runs the ordered task list of subdomain g
+// ([off[g], off[g + 1]) of the task array; every target is written by one
+// task, which reads only the inputs and the outputs of earlier tasks of the
+// list), one task after another.  The barrier between tasks orders the
+// global stores of one task before the loads of the next (one work-group,
+// one compute unit).
+template <typename T, int MODE, int NCB>
+__global__ __launch_bounds__(256, 2) void vseq_kernel(const VUpdTask *tasks, const int64_t *fuse, const int64_t *off,
+                                                   int nsub, const VUpdPair *pairs, const VDiagTask *vdiag, Bases b,
+                                                   VBases vb, DArrays D, int nrhs) {
+    using T2 = typename C2T<T>::type;
+    __shared__ SvSmem<T2, NCB> sm;
+    const int64_t g = xcd_task(nsub);
+    if (g >= nsub) return;
+    const int c0 = blockIdx.y * 16 * NCB;
+    const int ncol = min(16 * NCB, nrhs - c0);
+    const int64_t t0 = off[g], t1 = off[g + 1];
+    for (int64_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        vupd_task<T, MODE, NCB>(tasks[t], fuse[t], pairs, vdiag, b, vb, D, nrhs, c0, ncol, sm);
+    }
 }
 
 // XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
@@ -738,6 +793,27 @@ void launch_vupd_ncb(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, 
                            nrhs);
 }
 template <typename T>
+hipError_t launch_vseq(const VUpdTask *tasks, const int64_t *fuse, const int64_t *off, int nsub,
+                       const VUpdPair *pairs, const VDiagTask *vdiag, bool bwd, const Bases &b, const VBases &vb,
+                       const DArrays &D, int nrhs, int cols, hipStream_t s) {
+    if (nsub <= 0) return hipSuccess;
+    const int ncb = sv_ncb(nrhs, cols);
+    dim3 grid(sv_groups(nsub), (unsigned)((nrhs + 16 * ncb - 1) / (16 * ncb)));
+    if (ncb == 1) {
+        if (bwd) hipLaunchKernelGGL((vseq_kernel<T, 1, 1>), grid, dim3(256), 0, s, tasks, fuse, off, nsub, pairs, vdiag,
+                                    b, vb, D, nrhs);
+        else hipLaunchKernelGGL((vseq_kernel<T, 0, 1>), grid, dim3(256), 0, s, tasks, fuse, off, nsub, pairs, vdiag, b,
+                                vb, D, nrhs);
+    } else {
+        if (bwd) hipLaunchKernelGGL((vseq_kernel<T, 1, 2>), grid, dim3(256), 0, s, tasks, fuse, off, nsub, pairs, vdiag,
+                                    b, vb, D, nrhs);
+        else hipLaunchKernelGGL((vseq_kernel<T, 0, 2>), grid, dim3(256), 0, s, tasks, fuse, off, nsub, pairs, vdiag, b,
+                                vb, D, nrhs);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                        const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
                        int cols, hipStream_t s) {
@@ -817,6 +893,9 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
                                         const DArrays &, int, int, hipStream_t);                                  \
     template hipError_t launch_vupd<T>(const VUpdTask *, const int64_t *, int64_t, const VUpdPair *,            \
                                        const VDiagTask *, int, const Bases &, const VBases &, const DArrays &, int, \
+                                       int, hipStream_t);                                                         \
+    template hipError_t launch_vseq<T>(const VUpdTask *, const int64_t *, const int64_t *, int, const VUpdPair *,  \
+                                       const VDiagTask *, bool, const Bases &, const VBases &, const DArrays &, int, \
                                        int, hipStream_t);                                                         \
     template hipError_t launch_vgather_h<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);     \
     template hipError_t launch_vscatter_lam<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);  \

@@ -109,7 +109,9 @@ def test_graph_replays_match_eager_bitwise():
 
 @pytest.mark.parametrize("tune", [{"s1_block": 1}, {"s1_block": 4}, {"k_block": 1}, {"k_block": 8},
                                   {"lookahead_tasks": 1}, {"side_early": 1}, {"k_fuse": 1}, {"solve_cols": 16},
-                                  {"panel_rows": 16}, {"panel_rows": 16, "k_fuse": 1}])
+                                  {"panel_rows": 16}, {"panel_rows": 16, "k_fuse": 1}, {"solve_seq": 1},
+                                  {"solve_seq": 1, "solve_cols": 16}, {"solve_seq": 1, "s1_block": 4},
+                                  {"solve_narrow": 100000}, {"solve_narrow": 100000, "solve_seq": 1}])
 def test_tuning_variants_agree(tune):
     from paper_2002_05018_amd import Solver
     prob = W.make_problem(5, (2, 2, 1), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=40, seed=22)
@@ -132,7 +134,8 @@ def test_autotune_picks_a_valid_tuning():
     s.factor("fp64")
     want = s.solve(f).cpu().numpy()
     res = autotune(s, f, "fp64", repeats=1)
-    assert not res["cached"] and len(res["trials"]) == 18
+    from paper_2002_05018_amd.autotune import DEFAULT_SPACE
+    assert not res["cached"] and len(res["trials"]) == sum(len(v) for v in DEFAULT_SPACE.values())
     assert s.tuning() == res["tuning"]
     s.factor("fp64")
     assert_rhs_close(s.solve(f).cpu().numpy(), want, 1e-12, "autotuned")
