@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from parity import assert_rhs_close, factor_as_benchmarked, host_residual, load_fixture
+from parity import assert_rhs_close, factor_as_benchmarked, host_residual, load_fixture, rhs_max_rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -113,12 +113,14 @@ def test_config3_batch_against_oracle():
         systems.append(S)
     factor_as_benchmarked(b, fo.shape[0], "fp64")
     E = b.solve(torch.from_numpy(fo).cuda()).cpu().numpy()
-    worst = 0.0
+    rows = []
     for p, prob in enumerate(probs):
         fx = load_fixture(3, f"p{p}_")
         Ep = E[:, eo[p]:eo[p + 1]]
-        err = assert_rhs_close(Ep[:, fx["edges"]], fx["E"], 1e-10, f"problem {p} E", scale=fx["E_inf"])
+        err = rhs_max_rel(Ep[:, fx["edges"]], fx["E"], scale=fx["E_inf"])
         r = host_residual(systems[p], Ep, fo[:, eo[p]:eo[p + 1]])
-        assert np.all(r <= 1e-10), (p, r)
-        worst = max(worst, float(err.max()))
-    print(f"[parity] configuration 3: worst E error vs oracle {worst:.2e}", flush=True)
+        rows.append((p, prob.n, float(err.max()), float(r.max()), float(fx["residual"].max())))
+        print(f"[parity] configuration 3 problem {p} ({prob.n}^3): E error vs oracle {err.max():.2e}, "
+              f"residual {r.max():.2e} (oracle's own {fx['residual'].max():.2e})", flush=True)
+    for p, n, err, res, res_o in rows:
+        assert err <= 1e-10 and res <= 1e-10, (p, n, err, res, res_o)
