@@ -221,10 +221,12 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int6
                                                     DArrays D, int nrhs) {
     using T2 = typename C2T<T>::type;
     __shared__ SvSmem<T2, NCB> sm;
-    const int64_t task = xcd_task(ntask);
-    if (task >= ntask) return;
+    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
+    const int64_t item = xcd_task(ntask * nyb);
+    if (item >= ntask * nyb) return;
+    const int64_t task = item / nyb;
     const VDiagTask tk = tasks[task];
-    const int c0 = blockIdx.y * 16 * NCB;
+    const int c0 = (int)(item - task * nyb) * 16 * NCB;
     const int ncol = min(16 * NCB, nrhs - c0);
     T2 xr[4 * NCB], lf[16];
     if (BWD)
@@ -323,7 +325,10 @@ __global__ __launch_bounds__(256) void vdiag_multi_kernel(const VDiagTask *tasks
 }
 
 // out (-=|=|+=) sum_p op(L_p) src_p with op = identity (mode 0) or
-// transpose (modes 1, 2); blockIdx.y selects 16 NCB right-hand sides.  The
+// transpose (modes 1, 2); each work-group takes 16 NCB right-hand sides of a
+// task.  The column blocks of one task are consecutive items of one XCD's
+// range (xcd_task), so the factor tile they share is read from HBM once and
+// from that XCD's L2 after.  The
 // factor tile and X block of product p + 1 are fetched while product p runs.
 // When fuse[task] >= 0 this update is the last one its target receives before
 // the diagonal solve fuse[task] (forward: the target is that block's x;
@@ -442,9 +447,11 @@ __global__ __launch_bounds__(256, 2) void vupd_kernel(const VUpdTask *tasks, con
                                                    DArrays D, int nrhs) {
     using T2 = typename C2T<T>::type;
     __shared__ SvSmem<T2, NCB> sm;
-    const int64_t task = xcd_task(ntask);
-    if (task >= ntask) return;
-    const int c0 = blockIdx.y * 16 * NCB;
+    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
+    const int64_t item = xcd_task(ntask * nyb);
+    if (item >= ntask * nyb) return;
+    const int64_t task = item / nyb;
+    const int c0 = (int)(item - task * nyb) * 16 * NCB;
     vupd_task<T, MODE, NCB>(tasks[task], fuse[task], pairs, vdiag, b, vb, D, nrhs, c0, min(16 * NCB, nrhs - c0), sm);
 }
 
@@ -460,9 +467,11 @@ __global__ __launch_bounds__(256, 2) void vseq_kernel(const VUpdTask *tasks, con
                                                    VBases vb, DArrays D, int nrhs) {
     using T2 = typename C2T<T>::type;
     __shared__ SvSmem<T2, NCB> sm;
-    const int64_t g = xcd_task(nsub);
-    if (g >= nsub) return;
-    const int c0 = blockIdx.y * 16 * NCB;
+    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
+    const int64_t item = xcd_task((int64_t)nsub * nyb);
+    if (item >= (int64_t)nsub * nyb) return;
+    const int64_t g = item / nyb;
+    const int c0 = (int)(item - g * nyb) * 16 * NCB;
     const int ncol = min(16 * NCB, nrhs - c0);
     const int64_t t0 = off[g], t1 = off[g + 1];
     for (int64_t t = t0; t < t1; ++t) {
@@ -761,7 +770,7 @@ hipError_t launch_vdiag(const VDiagTask *tasks, int64_t ntask, int maxt, bool bw
     if (ntask <= 0) return hipSuccess;
     if (maxt <= 1) {
         const int ncb = sv_ncb(nrhs, cols);
-        dim3 grid(sv_groups(ntask), (unsigned)((nrhs + 16 * ncb - 1) / (16 * ncb)));
+        dim3 grid(sv_groups(ntask * ((nrhs + 16 * ncb - 1) / (16 * ncb))));
         if (ncb == 1) {
             if (bwd) hipLaunchKernelGGL((vdiag_kernel<T, true, 1>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
             else hipLaunchKernelGGL((vdiag_kernel<T, false, 1>), grid, dim3(256), 0, s, tasks, ntask, b, vb, D, nrhs);
@@ -781,7 +790,7 @@ template <typename T, int NCB>
 void launch_vupd_ncb(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask, const VUpdPair *pairs,
                      const VDiagTask *vdiag, int mode, const Bases &b, const VBases &vb, const DArrays &D, int nrhs,
                      hipStream_t s) {
-    dim3 grid(sv_groups(ntask), (unsigned)((nrhs + 16 * NCB - 1) / (16 * NCB)));
+    dim3 grid(sv_groups(ntask * ((nrhs + 16 * NCB - 1) / (16 * NCB))));
     if (mode == 0)
         hipLaunchKernelGGL((vupd_kernel<T, 0, NCB>), grid, dim3(256), 0, s, tasks, fuse, ntask, pairs, vdiag, b, vb, D,
                            nrhs);
@@ -798,7 +807,7 @@ hipError_t launch_vseq(const VUpdTask *tasks, const int64_t *fuse, const int64_t
                        const DArrays &D, int nrhs, int cols, hipStream_t s) {
     if (nsub <= 0) return hipSuccess;
     const int ncb = sv_ncb(nrhs, cols);
-    dim3 grid(sv_groups(nsub), (unsigned)((nrhs + 16 * ncb - 1) / (16 * ncb)));
+    dim3 grid(sv_groups((int64_t)nsub * ((nrhs + 16 * ncb - 1) / (16 * ncb))));
     if (ncb == 1) {
         if (bwd) hipLaunchKernelGGL((vseq_kernel<T, 1, 1>), grid, dim3(256), 0, s, tasks, fuse, off, nsub, pairs, vdiag,
                                     b, vb, D, nrhs);
