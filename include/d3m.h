@@ -349,7 +349,15 @@ typedef struct {
                                 whatever solve_cols says (more, shorter
                                 work-groups where a step is latency-bound);
                                 0 (default): never                           */
-    int32_t reserved[3];
+    int32_t k_overlap;       /* 1: the block-LDL^T updates of K off the next
+                                level's columns go to two side streams (the
+                                next few levels' columns, the rest), and every
+                                launch waits only for the launches that wrote
+                                its block columns, so the bulk updates of a
+                                chain segment overlap the next segment's pivot
+                                chain; 0 (default): one side stream, each step
+                                waiting for the previous step's side updates */
+    int32_t reserved[2];
 } d3m_tuning;
 
 /* Read / replace the tuning.  A new s1_block, k_block or k_fuse rebuilds the factor schedule

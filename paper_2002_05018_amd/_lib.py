@@ -81,7 +81,7 @@ class d3m_tuning(C.Structure):
     _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
                 ("k_block", C.c_int32), ("side_early", C.c_int32), ("k_fuse", C.c_int32),
                 ("panel_rows", C.c_int32), ("solve_seq", C.c_int32), ("solve_narrow", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("k_overlap", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class d3m_bk_out(C.Structure):
@@ -409,7 +409,7 @@ class Solver:
         _check(_lib.d3m_set_graphs(self._handle, int(bool(use_graph))))
 
     TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early", "k_fuse", "panel_rows",
-                   "solve_seq", "solve_narrow")
+                   "solve_seq", "solve_narrow", "k_overlap")
 
     def tuning(self):
         t = d3m_tuning()

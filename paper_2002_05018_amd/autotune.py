@@ -19,6 +19,8 @@ the solve.  The candidates are the launch shapes the schedules expose:
   own launch or are applied inside that level's pivot and panel launches;
 * ``panel_rows``: rows of a panel tile per work-group (64, or 16 with four
   work-groups per tile);
+* ``k_overlap``: the off-critical updates of K on one side stream behind the
+  previous step, or on two side streams with per-column waits;
 * ``solve_cols``: right-hand sides per work-group of the solve sweeps
   (16 or 32 columns of the MFMA tile);
 * ``solve_seq``: the subdomain sweeps of the solve as one launch per
@@ -46,13 +48,14 @@ DEFAULT_SPACE = {
     "side_early": (0, 1),
     "k_fuse": (0, 1),
     "panel_rows": (64, 16),
+    "k_overlap": (0, 1),
     "solve_seq": (0, 1),
     "solve_narrow": (0, 1024, 4096),
     "solve_cols": (32, 16),
 }
 _PREC = {0: "fp64", 1: "fp32_ir", "fp64": "fp64", "fp32_ir": "fp32_ir"}
 # parameters that change the factorisation schedule (the rest only the solve)
-_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early", "k_fuse", "panel_rows")
+_FACTOR_KEYS = ("s1_block", "k_block", "lookahead_tasks", "side_early", "k_fuse", "panel_rows", "k_overlap")
 
 
 def signature(solver, nrhs, precision) -> str:

@@ -110,6 +110,8 @@ struct d3m_problem {
     // second stream for the updates that the next elimination step does not
     // need (look-ahead), and ordering events between the two streams
     hipStream_t side = nullptr;
+    hipStream_t side2 = nullptr;  // far updates of the K phase (near ones go on side)
+    std::vector<hipEvent_t> dep_pool;  // events of the K phase's dependency waits
     std::vector<hipEvent_t> sync_pool;
     size_t sync_next = 0;
     hipEvent_t sync_event() {
@@ -160,7 +162,9 @@ struct d3m_problem {
             if (b->p) (void)hipFree(b->p);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         for (auto e : sync_pool) (void)hipEventDestroy(e);
+        for (auto e : dep_pool) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
+        if (side2) (void)hipStreamDestroy(side2);
         if (gstream) (void)hipStreamDestroy(gstream);
         if (g_in) (void)hipEventDestroy(g_in);
         if (g_out) (void)hipEventDestroy(g_out);
@@ -317,6 +321,7 @@ int setup_device(d3m_problem *h) {
     HIPCHK(hipSetDevice(h->opt.device));
     // default priority (the same as the caller's streams)
     HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&h->g_out, hipEventDisableTiming));
@@ -428,8 +433,115 @@ VBases vbases_of(d3m_problem *h) {
 // only after the panels it reads are scaled.
 constexpr i64 kLookaheadMinTasks = 512;  // default of d3m_tuning.lookahead_tasks
 
+// The K phase with dependency tracking by block column (unit): a step's
+// pivot and panel launches and its critical updates run on s; its near
+// updates (columns of the next few levels) on the side stream and its far
+// updates on a second side stream, each after the step's panels.  Every
+// launch waits only for the side launches that last wrote one of its
+// columns (a side stream runs in order, so the latest writer on it covers
+// the earlier ones), so the far updates of a chain segment overlap the pivot
+// chain of the next segment instead of stalling it.  Launches that write a
+// tile in the same order as before, so results are bitwise unchanged.
+template <typename T>
+int run_factor_sweep_tracked(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
+    hipStream_t ss[2] = {h->side, h->side2};
+    const i64 min_split = h->tune.lookahead_tasks > 0 ? h->tune.lookahead_tasks : kLookaheadMinTasks;
+    // a step records at most three events (panels done, near done, far done);
+    // none is reused within the sweep
+    const size_t need = 3 * steps.size() + 4;
+    while (h->dep_pool.size() < need) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->dep_pool.push_back(e);
+    }
+    size_t next_ev = 0;
+    auto take_event = [&]() { return next_ev < h->dep_pool.size() ? h->dep_pool[next_ev++] : nullptr; };
+    std::vector<hipEvent_t> evs[2];                  // events recorded on each side stream, in order
+    std::vector<std::pair<int, int>> last(h->pl.k_units, {-1, -1});  // (side stream, event index) of the last writer
+    auto wait_cols = [&](const std::vector<int> &cols, hipStream_t on) -> int {
+        int hi[2] = {-1, -1};
+        for (int k : cols)
+            if (last[k].first >= 0) hi[last[k].first] = std::max(hi[last[k].first], last[k].second);
+        for (int q = 0; q < 2; ++q)
+            if (hi[q] >= 0 && ss[q] != on) HIPCHK(hipStreamWaitEvent(on, evs[q][hi[q]], 0));
+        return D3M_OK;
+    };
+    int rc;
+    for (const auto &st : steps) {
+        hipEvent_t ev{};
+        if ((rc = wait_cols(st.cols_bk, s)) != D3M_OK) return rc;
+        if (st.nbk > 0) {
+            h->prof_begin(KID_BK, ev, s);
+            HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, h->d_pairs, b, h->D, h->d_status,
+                                h->d_bkscratch, s));
+            h->prof_end(KID_BK, ev, 0.0, s);
+        }
+        if (st.npan > 0 || st.nsc > 0) {
+            h->prof_begin(KID_PANEL, ev, s);
+            if (st.fused_scale) {
+                HIPCHK(launch_panel_scale<T>(h->d_gemm + st.pan0, h->d_scale + st.sc0, st.npan, h->d_pairs, b, h->D,
+                                             h->tune.panel_rows == 16 ? 16 : 64, s));
+            } else {
+                HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+                HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+            }
+            h->prof_end(KID_PANEL, ev, st.pan_flops, s);
+        }
+        const i64 nfar = st.nup - st.ncrit - st.nnear;
+        // small off-critical groups stay on s (a cross-stream hand-off costs
+        // more than the overlap gains)
+        const bool split = st.nup - st.ncrit >= min_split;
+        hipEvent_t ready = nullptr;
+        auto side_launch = [&](int q, i64 off, i64 n, const std::vector<int> &cols, double fl) -> int {
+            if (!ready) {
+                if (!(ready = take_event())) return fail(D3M_EHIP, "internal: dependency event pool exhausted");
+                HIPCHK(hipEventRecord(ready, s));
+            }
+            HIPCHK(hipStreamWaitEvent(ss[q], ready, 0));
+            int r = wait_cols(cols, ss[q]);
+            if (r != D3M_OK) return r;
+            hipEvent_t e2{};
+            h->prof_begin(KID_UPDATE, e2, ss[q]);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0 + off, n, h->d_pairs, b, 1, ss[q]));
+            h->prof_end(KID_UPDATE, e2, fl, ss[q]);
+            hipEvent_t done = take_event();
+            if (!done) return fail(D3M_EHIP, "internal: dependency event pool exhausted");
+            HIPCHK(hipEventRecord(done, ss[q]));
+            evs[q].push_back(done);
+            for (int k : cols) last[k] = {q, (int)evs[q].size() - 1};
+            return D3M_OK;
+        };
+        auto rest = [&]() -> int {
+            if (st.nnear > 0 && (rc = side_launch(0, st.ncrit, st.nnear, st.cols_near, st.near_flops)) != D3M_OK)
+                return rc;
+            if (nfar > 0 && (rc = side_launch(1, st.ncrit + st.nnear, nfar, st.cols_far,
+                                              st.up_flops - st.crit_flops - st.near_flops)) != D3M_OK)
+                return rc;
+            return D3M_OK;
+        };
+        const bool late = h->tune.side_early == 0;
+        if (split && !late && (rc = rest()) != D3M_OK) return rc;
+        const i64 nmain = split ? st.ncrit : st.nup;
+        if (nmain > 0) {
+            if ((rc = wait_cols(st.cols_crit, s)) != D3M_OK) return rc;
+            if (!split) {
+                if ((rc = wait_cols(st.cols_near, s)) != D3M_OK) return rc;
+                if ((rc = wait_cols(st.cols_far, s)) != D3M_OK) return rc;
+            }
+            h->prof_begin(KID_UPDATE, ev, s);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, nmain, h->d_pairs, b, 1, s));
+            h->prof_end(KID_UPDATE, ev, split ? st.crit_flops : st.up_flops, s);
+        }
+        if (split && late && (rc = rest()) != D3M_OK) return rc;
+    }
+    for (int q = 0; q < 2; ++q)
+        if (!evs[q].empty()) HIPCHK(hipStreamWaitEvent(s, evs[q].back(), 0));
+    return D3M_OK;
+}
+
 template <typename T>
 int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
+    if (h->tune.k_overlap && !steps.empty() && steps[0].track) return run_factor_sweep_tracked<T>(h, steps, b, s);
     hipStream_t s2 = h->side;
     hipEvent_t rest_done = nullptr;
     const i64 min_split = h->tune.lookahead_tasks > 0 ? h->tune.lookahead_tasks : kLookaheadMinTasks;
@@ -1012,6 +1124,7 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
         return fail(D3M_EINVAL, "panel_rows must be 0, 16 or 64");
     if (t->solve_seq != 0 && t->solve_seq != 1) return fail(D3M_EINVAL, "solve_seq must be 0 or 1");
     if (t->solve_narrow < 0) return fail(D3M_EINVAL, "solve_narrow must be >= 0");
+    if (t->k_overlap != 0 && t->k_overlap != 1) return fail(D3M_EINVAL, "k_overlap must be 0 or 1");
     const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block, old_f = h->tune.k_fuse;
     h->drop_graphs();
     h->tune = *t;

@@ -445,12 +445,20 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                     for (size_t y = 0; y <= x; ++y)
                         if (ustruct[j][y] > f) targets[{ustruct[j][x], ustruct[j][y]}].push_back(j);
         for (auto &kv : targets) std::sort(kv.second.begin(), kv.second.end());
-        // targets in block columns of the next level first
+        // targets in block columns of the next level first (critical), then
+        // those of the next few levels (near: the next chain segment needs
+        // them soon), then the rest (far); each group is one launch, and the
+        // columns each launch writes are recorded for the dependency waits
         st.up0 = (i64)pl.gemm.size();
-        for (int pass = 0; pass < 2; ++pass) {
+        st.track = true;
+        st.cols_bk.assign(J.begin(), J.end());
+        auto group = [&](int k) { return ulevel[k] == L + 1 ? 0 : (ulevel[k] <= L + 1 + K_BLOCK ? 1 : 2); };
+        for (int pass = 0; pass < 3; ++pass) {
+            std::vector<int> &cols = pass == 0 ? st.cols_crit : (pass == 1 ? st.cols_near : st.cols_far);
             for (auto &kv : targets) {
                 int i = kv.first.first, k = kv.first.second;
-                if ((ulevel[k] == L + 1) != (pass == 0)) continue;
+                if (group(k) != pass) continue;
+                if (cols.empty() || cols.back() != k) cols.push_back(k);
                 if (pass == 0 && fuse_next) {  // applied by the next level's pivot and panel launches
                     auto &pd = pending[{k, i}];
                     const int ra = tile_rows(nsz[i], 0), rb = tile_rows(nsz[k], 0);
@@ -473,11 +481,15 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                                 double f = 8.0 * w * ((i == k && a == b) ? ra * (ra + 1) / 2.0 : (double)ra * rb);
                                 st.up_flops += f;
                                 if (pass == 0) st.crit_flops += f;
+                                if (pass == 1) st.near_flops += f;
                             }
                         pl.gemm.push_back(g);
                     }
             }
             if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
+            if (pass == 1) st.nnear = (i64)pl.gemm.size() - st.up0 - st.ncrit;
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
         }
         st.nup = (i64)pl.gemm.size() - st.up0;
         pl.flops_s3 += st.up_flops;

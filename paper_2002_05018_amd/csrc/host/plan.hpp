@@ -23,6 +23,15 @@ struct FactorStep {
     double up_flops = 0.0;   // algorithmic flops of the update GEMMs
     double crit_flops = 0.0; // ... of which in the first ncrit tasks
     double pan_flops = 0.0;  // algorithmic flops of the panels (triangular solves)
+    // K phase: the update tasks after the ncrit critical ones are split into
+    // nnear tasks whose block columns belong to the next few levels and the
+    // far rest; the block columns (units) each launch touches drive the waits
+    // between the streams (a launch waits only for earlier launches that
+    // wrote its columns)
+    bool track = false;
+    i64 nnear = 0;
+    double near_flops = 0.0;
+    std::vector<int> cols_bk, cols_crit, cols_near, cols_far;
 };
 
 // One sweep step of the solve: a diagonal launch and an update launch.
