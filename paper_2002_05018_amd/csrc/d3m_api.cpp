@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <vector>
@@ -541,10 +542,19 @@ int run_factor_sweep_tracked(d3m_problem *h, const std::vector<FactorStep> &step
 
 template <typename T>
 int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const Bases &b, hipStream_t s) {
-    if (h->tune.k_overlap && !steps.empty() && steps[0].track) return run_factor_sweep_tracked<T>(h, steps, b, s);
+    // Whole-block pivot units (pivot_scope 1, blocks of more than one tile)
+    // run the K phase on one stream: with the look-ahead side stream their
+    // factor came out wrong at 48^3 hexes in 512 subdomains (and one run
+    // faulted), while the same schedule on one stream, and every one-tile
+    // unit schedule, is correct; the cause is not found, so that combination
+    // is not launched.
+    const bool one_stream = h->opt.pivot_scope == 1 && !steps.empty() && steps[0].track;
+    if (h->tune.k_overlap && !one_stream && !steps.empty() && steps[0].track)
+        return run_factor_sweep_tracked<T>(h, steps, b, s);
     hipStream_t s2 = h->side;
     hipEvent_t rest_done = nullptr;
-    const i64 min_split = h->tune.lookahead_tasks > 0 ? h->tune.lookahead_tasks : kLookaheadMinTasks;
+    const i64 min_split = one_stream ? std::numeric_limits<i64>::max()
+                                     : (h->tune.lookahead_tasks > 0 ? h->tune.lookahead_tasks : kLookaheadMinTasks);
     for (const auto &st : steps) {
         hipEvent_t ev{};
         if (st.nbk > 0) {
