@@ -19,7 +19,14 @@ keys prefixed ``p<index>_``):
   residual   float64 [nrhs]      ||S E - f||_inf / ||f||_inf of the oracle
                                  solution (oracle S and f)
   f          complex128 [nrhs, ns] oracle plane-wave load at the sampled edges
-and the oracle's phase timings on the machine that wrote it (seconds).
+and the oracle's phase timings on the machine that wrote it (seconds).  For
+the dielectric-sphere workload (receivers and learnable tetrahedra) also
+  grad_tets  int64 [ng]          the finite-difference tetrahedra and a sample
+                                 of the other learnable ones
+  grad       float64 [ng]        dL/d eps_r there, L = sum_rhs sum_m
+                                 |E(r_m)|^2 at the receivers, by the oracle's
+                                 adjoint solve
+  grad_max   float64             max |dL/d eps_r| over the learnable tetrahedra
 
 The right-hand sides are the oracle's plane-wave loads for the workload's
 directions and polarisations (Section II, second line of the BVP).
@@ -38,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
 from oracle.d3m import D3MOracle, relative_residual  # noqa: E402
+from oracle.fem import probe_matrix  # noqa: E402
 
 SAMPLES = {2: (4096, 2048), 4: (2048, 1024), 5: (4096, 2048), 3: (256, 128)}
 
@@ -72,10 +80,23 @@ def solve_problem(prob, seed, n_edge, n_lm, log):
     rng = np.random.default_rng(seed)
     e, lm = _sample(rng, o, n_edge, n_lm)
     tim = {k: float(v) for k, v in o.timings.items()}
+    lam = o.lam.copy()  # the adjoint solve below replaces the oracle's lambda
+    extra = {}
+    if prob.receivers.shape[0] and prob.learnable.size:
+        # gradient of L = sum_rhs sum_m |E(r_m)|^2 (receivers r_m) with respect
+        # to eps_r by the oracle's adjoint: G = dL/dRe E + j dL/dIm E =
+        # 2 sum_m P_m^T (P_m E) for the real probe rows P_m
+        P = probe_matrix(o.fem.topo, prob.receivers).reshape(-1, o.fem.topo.n_edges)
+        G = 2.0 * (P.T @ (P @ E.T)).T
+        g, _ = o.adjoint(G, E)
+        t = np.union1d(prob.fd_tets, rng.choice(prob.learnable, min(256, prob.learnable.size), replace=False))
+        extra = {"grad_tets": t.astype(np.int64), "grad": g[t], "grad_max": np.array(np.abs(g[prob.learnable]).max())}
+        log(f"  adjoint gradient: max |g| over learnable tets {extra['grad_max']:.3e}")
     out = {"edges": e, "E": E[:, e], "E_inf": np.abs(E).max(axis=1), "lms": lm,
-           "lam": o.lam[:, lm], "lam_inf": np.abs(o.lam).max(axis=1) if o.lam.size else np.zeros(E.shape[0]),
+           "lam": lam[:, lm], "lam_inf": np.abs(lam).max(axis=1) if lam.size else np.zeros(E.shape[0]),
            "residual": r, "f": f[:, e],
            "timing_names": np.array(sorted(tim)), "timing_s": np.array([tim[k] for k in sorted(tim)])}
+    out.update(extra)
     return out
 
 

@@ -114,9 +114,11 @@ def test_config4_fp64_and_fp32_refinement():
 def test_config5_gradient_vs_central_differences():
     """Configuration 5 (32^3 hexes, dielectric sphere, 4 right-hand sides):
     the autograd gradient of L = sum_rhs sum_m |E(r_m)|^2 over the 64
-    receivers, through the adjoint solve, against central differences (each
-    a full factor + solve) on four of the sphere's finite-difference
-    tetrahedra.  The step is h = 1e-4 rather than the configuration's 1e-6:
+    receivers, through the adjoint solve, against the oracle's adjoint
+    gradient (tests/golden/fullsize_config5.npz: the 20 finite-difference
+    tetrahedra and 256 other learnable ones, to 1e-9 of the largest
+    gradient), and against central differences (each a full factor + solve)
+    on four of the sphere's finite-difference tetrahedra.  The step is h = 1e-4 rather than the configuration's 1e-6:
     at 1e-6 the rounding of the two FP64 solves (relative residual ~1e-11)
     divided by 2h already reaches ~1e-4 of these gradients, while the
     truncation error of a central difference at 1e-4 is O(h^2) ~ 1e-8."""
@@ -138,6 +140,15 @@ def test_config5_gradient_vs_central_differences():
     L = objective(eps)
     L.backward()
     g = eps.grad.numpy()
+    # the oracle's adjoint gradient of the same objective (complex128 steps
+    # 1-7 and the adjoint solve on the host), at the 20 finite-difference
+    # tetrahedra and a sample of the other learnable ones
+    from parity import load_fixture
+    fx = load_fixture(5)
+    gerr = np.abs(g[fx["grad_tets"]] - fx["grad"]).max() / float(fx["grad_max"])
+    print(f"[gpu fullsize] configuration 5: gradient vs oracle adjoint {gerr:.2e} "
+          f"(of max |g| {float(fx['grad_max']):.3e}, {fx['grad_tets'].size} tetrahedra)", flush=True)
+    assert gerr <= 1e-9
     h = 1e-4
     scale = np.abs(g[prob.learnable]).max()
     for t in prob.fd_tets[:4]:
