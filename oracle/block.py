@@ -17,6 +17,17 @@
   L_ij = P_i^T W_ij and P = blkdiag(P_j).
 * Step 6: forward, diagonal and backward substitution in the same block
   order.
+* The multifrontal form of step 5 (named after the seven steps of Section
+  II as a way to speed the block LDL^T up): the same factors, with the
+  Schur updates gathered in the elimination tree instead of applied in
+  place.  The parent of j is the first block of struct(j); the front of j
+  is block column j of K plus the update matrices of j's children added in
+  at their rows and columns (extend-add), and after j's pivot block and
+  panels are formed its own update matrix
+      U_j[i, k] = F_j[i, k] - X_ij W_kj^T      (i >= k in struct(j))
+  goes to the parent.  F_j[i, k] for i, k in struct(j) holds only the
+  children's contributions: the entries of K there belong to the front of
+  block k.
 """
 from __future__ import annotations
 
@@ -167,3 +178,59 @@ class BlockLDLT:
             Pi = np.eye(self.sizes[i])[:, self.diag[i].perm]
             L[off[i]:off[i + 1], off[j]:off[j + 1]] = Pi.T @ W
         return P @ L @ D @ L.T @ P.T
+
+
+def tree_parent(struct):
+    """Parent of every block in the elimination tree: the first block of
+    struct(j), -1 for a root."""
+    return [s[0] if s else -1 for s in struct]
+
+
+class MultifrontalLDLT(BlockLDLT):
+    """Step 5 in multifrontal form: same factors as ``BlockLDLT`` (up to the
+    order of rounding), the updates carried by update matrices.  ``update``
+    keeps every block's update matrix U_j as a dict over (i, k), i >= k in
+    struct(j)."""
+
+    def __init__(self, Kb, sizes, struct, pivoting=True):
+        self.sizes = list(sizes)
+        self.struct = struct
+        l = len(sizes)
+        parent = tree_parent(struct)
+        children = [[] for _ in range(l)]
+        for c, p in enumerate(parent):
+            if p >= 0:
+                children[p].append(c)
+        self.diag = []
+        self.Lhat = {}
+        self.update = []
+        for j in range(l):
+            rows = [j] + list(struct[j])
+            # front of j: block column j of K, then every child's update
+            # matrix added at its own rows and columns
+            F = {}
+            for a, i in enumerate(rows):
+                for k in rows[:a + 1]:
+                    F[(i, k)] = np.zeros((sizes[i], sizes[k]), np.complex128)
+            for i in rows:
+                if (i, j) in Kb:
+                    F[(i, j)] += Kb[(i, j)]
+            for c in children[j]:
+                for (i, k), U in self.update[c].items():
+                    if (i, k) not in F:
+                        raise ValueError(f"update matrix of {c} reaches ({i}, {k}) outside the front of {j}")
+                    F[(i, k)] += U
+            f = bk_ldlt(F[(j, j)], pivoting=pivoting)
+            self.diag.append(f)
+            Dinv = f.dinv()
+            X, W = {}, {}
+            for i in struct[j]:
+                Kp = F[(i, j)][:, f.perm]                          # F_ij P_j
+                X[i] = sla.solve_triangular(f.L, Kp.T, lower=True, unit_diagonal=True).T
+                W[i] = X[i] @ Dinv
+                self.Lhat[(i, j)] = W[i]
+            U = {}
+            for a, i in enumerate(struct[j]):
+                for k in struct[j][:a + 1]:
+                    U[(i, k)] = F[(i, k)] - X[i] @ W[k].T
+            self.update.append(U)

@@ -1,7 +1,8 @@
 """The seven steps of D3M (Section II) end to end, plus the adjoint -- oracle.
 
 Step 1-2 (``ddm.DomainMatrices``), steps 3-4 (``block.nested_dissection_boxes``
-and ``block.symbolic``), step 5 (``block.BlockLDLT``), step 6
+and ``block.symbolic``), step 5 (``block.BlockLDLT``, or its multifrontal form
+``block.MultifrontalLDLT``), step 6
 (``BlockLDLT.solve``) and step 7 (``DomainMatrices.recover``).
 
 Adjoint (a reading: the paper does not differentiate).  S is complex
@@ -20,7 +21,7 @@ import time
 import numpy as np
 import scipy.sparse.linalg as sla
 
-from .block import BlockLDLT, clique_adjacency, nested_dissection_boxes, symbolic
+from .block import BlockLDLT, MultifrontalLDLT, clique_adjacency, nested_dissection_boxes, symbolic
 from .ddm import Decomposition, DomainMatrices
 from .fem import GlobalFEM
 
@@ -29,12 +30,13 @@ class D3MOracle:
     """Reference D3M solver for a ``workloads.Problem``-like set of arrays."""
 
     def __init__(self, xyz, tets, part, eps_r, k, alpha, parts=None, order=None,
-                 pivoting=True):
+                 pivoting=True, multifrontal=False):
         t0 = time.perf_counter()
         self.fem = GlobalFEM(xyz, tets, eps_r, k)
         self.dec = Decomposition(self.fem, part, alpha)
         self.parts = parts
         self.pivoting = pivoting
+        self.multifrontal = multifrontal
         self.timings = {"setup": time.perf_counter() - t0}
         self._order = order
 
@@ -65,7 +67,8 @@ class D3MOracle:
         sizes = [int(dec.block_start[b + 1] - dec.block_start[b]) for b in order]
         Kpos = {(int(pos[P]), int(pos[Q])): v for (P, Q), v in Kb.items() if pos[P] >= pos[Q]}
         t3 = time.perf_counter()
-        self.ldlt = BlockLDLT(Kpos, sizes, self.struct, pivoting=self.pivoting)
+        method = MultifrontalLDLT if self.multifrontal else BlockLDLT
+        self.ldlt = method(Kpos, sizes, self.struct, pivoting=self.pivoting)
         t4 = time.perf_counter()
         self.timings.update(domain_matrices=t1 - t0, assemble=t2 - t1,
                             order_symbolic=t3 - t2, block_ldlt=t4 - t3)
