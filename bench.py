@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--batch-count", type=int, default=32, help="problems of the configuration 3 batch")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--multifrontal", action="store_true",
+                    help="step 5 in its multifrontal form (update matrices and extend-adds) instead of the "
+                         "right-looking in-place updates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shapes instead of the autotuner's choice")
@@ -277,6 +280,7 @@ def bench_batch(args):
     tuned = autotune(solver, f, FP64, repeats=1, cache=args.tune_cache,
                      log=lambda m: print(m, file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
+    info = solver.query()  # algorithmic counts of the schedule the tuning selected
     ms, wall_ms = timed_steps(solver, FP64, f, E, args.steps, args.warmup, torch)
     _, sinfo = solver.solve(f, out=E, with_info=True)
     # the update-GEMM roofline from one eager pass with HIP events on its launches
@@ -363,7 +367,7 @@ def main():
     # timed steps time only the update GEMM launches (HIP events on their
     # streams); a separate untimed pass with every kernel group timed gives
     # the phase breakdown
-    solver = Solver.from_problem(prob, profile=1)
+    solver = Solver.from_problem(prob, profile=1, multifrontal=args.multifrontal)
     setup_s = time.perf_counter() - t0
     info = solver.info
     f_host = solver.rhs_planewave(prob.dirs, prob.pols)
@@ -379,6 +383,7 @@ def main():
         tuning["fp64"] = autotune(solver, f, FP64, cache=args.tune_cache)["tuning"]
         tune_s += time.perf_counter() - t0
 
+    info = solver.query()  # algorithmic counts of the schedule the tuning selected
     ms, wall_ms = timed_steps(solver, FP64, f, E, args.steps, args.warmup, torch)
     up = solver.kernel_stats("update_gemm")
     solver.set_profile(2)
@@ -414,8 +419,10 @@ def main():
                                f"k={prob.k:.4f}; FP64 factor+solve, FP32 factor + FP64 refinement "
                                f"to 1e-10 side by side",
                    "n_edges": info["n_edges"], "n_lm": info["n_lm"], "n_blocks": info["n_blocks"],
-                   "n_subdomains": info["n_subdomains"], "nrhs": prob.nrhs, "precision": "fp64"},
-        "roofline": _roofline(up, info, args.steps, "c128", measured_traffic(args.config, "fp64")),
+                   "n_subdomains": info["n_subdomains"], "nrhs": prob.nrhs, "precision": "fp64",
+                   "step5": "multifrontal" if args.multifrontal else "right-looking"},
+        "roofline": _roofline(up, info, args.steps, "c128",
+                              None if args.multifrontal else measured_traffic(args.config, "fp64")),
         "phases_ms_per_step": dict(phases, note="separate untimed pass with every kernel group timed "
                                                 "(the two streams overlap, so phases do not add up)"),
         "unknowns_per_s": info["n_edges"] / (ms / 1e3),
@@ -443,6 +450,7 @@ def main():
             t0 = time.perf_counter()
             tuning["fp32_ir"] = autotune(solver, f, FP32_IR, cache=args.tune_cache)["tuning"]
             tune_s += time.perf_counter() - t0
+        info32 = solver.query()
         ms32, _ = timed_steps(solver, FP32_IR, f, E, args.steps, args.warmup, torch)
         up32 = solver.kernel_stats("update_gemm")
         _, sinfo32 = solver.solve(f, out=E, with_info=True)
@@ -453,8 +461,13 @@ def main():
                              "error_vs_oracle": error_vs_oracle(E32_host, args.config),
                              "max_rel_diff_vs_fp64": diff,
                              "speedup_vs_fp64": ms / ms32,
-                             "roofline": _roofline(up32, info, args.steps, "c64",
-                                                   measured_traffic(args.config, "fp32_ir"))}
+                             "roofline": _roofline(up32, info32, args.steps, "c64",
+                                                   None if args.multifrontal
+                                                   else measured_traffic(args.config, "fp32_ir"))}
+    if args.multifrontal:
+        result["multifrontal"] = {"pool_bytes": info["mf_pool_bytes"], "update_matrix_bytes": info["mf_update_bytes"],
+                                  "extend_add_bytes": info["mf_extend_add_bytes"],
+                                  "extend_add_ms": phases["assembly"]}
     result["config"]["tuning"] = tuning or "defaults"
     result["autotune_s"] = tune_s
     if not args.no_cpu_baseline:

@@ -111,7 +111,16 @@ typedef struct {
                              factor of -K (one pass over its off-diagonal
                              tiles) and falls back to the whole-block scope
                              when it exceeds 10^growth_limit_log10          */
-    int32_t reserved[4];
+    int32_t k_multifrontal; /* 0 (default): step 5 right-looking, every unit's
+                             Schur updates applied in place to the block
+                             columns of its structure; 1: its multifrontal
+                             form (the variant named after the seven steps of
+                             Section II): a unit's updates go to its update
+                             matrix, which its parent's front adds in
+                             (extend-add).  Same factors up to the order of
+                             rounding; needs an extra pool of update
+                             matrices (d3m_info.mf_pool_bytes)               */
+    int32_t reserved[3];
 } d3m_options;
 
 typedef struct {
@@ -156,6 +165,15 @@ typedef struct {
                                  at most 64 rows, 1 whole blocks)             */
     int32_t pivot_fallbacks;  /* factorisations redone with the whole-block
                                  scope (options.pivot_fallback)               */
+    int32_t k_multifrontal;   /* 1 when step 5 runs in multifrontal form      */
+    int32_t pad0;
+    double mf_pool_bytes;     /* device bytes of the update-matrix pool of one
+                                 precision (complex128; half for FP32_IR), 0
+                                 in the right-looking form                    */
+    double mf_update_bytes;   /* bytes of all update matrices of one
+                                 factorisation without reuse (complex128)     */
+    double mf_extend_add_bytes; /* bytes the extend-adds of one factorisation
+                                 read and write (complex128)                  */
 } d3m_info;
 
 typedef struct {

@@ -58,7 +58,8 @@ class d3m_options(C.Structure):
     _fields_ = [("host_only", C.c_int32), ("quad_points", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
                 ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32), ("s1_block", C.c_int32),
-                ("pivot_fallback", C.c_int32), ("growth_limit_log10", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("pivot_fallback", C.c_int32), ("growth_limit_log10", C.c_int32), ("k_multifrontal", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class d3m_info(C.Structure):
@@ -70,7 +71,9 @@ class d3m_info(C.Structure):
                 ("factored", C.c_int32), ("n_units", C.c_int32), ("n_unit_levels", C.c_int32),
                 ("n_problems", C.c_int32), ("array_bytes", C.c_int64), ("mfma_flops_update", C.c_double),
                 ("bytes_update_gemm", C.c_double), ("solve_vector_bytes", C.c_double),
-                ("pivot_scope", C.c_int32), ("pivot_fallbacks", C.c_int32)]
+                ("pivot_scope", C.c_int32), ("pivot_fallbacks", C.c_int32), ("k_multifrontal", C.c_int32),
+                ("pad0", C.c_int32), ("mf_pool_bytes", C.c_double), ("mf_update_bytes", C.c_double),
+                ("mf_extend_add_bytes", C.c_double)]
 
 
 class d3m_batch_item(C.Structure):
@@ -162,7 +165,8 @@ def _stream_handle(stream):
 
 
 def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10,
-             pivot_scope=0, s1_block=0, use_graph=False, pivot_fallback=True, growth_limit_log10=0):
+             pivot_scope=0, s1_block=0, use_graph=False, pivot_fallback=True, growth_limit_log10=0,
+             multifrontal=False):
     opt = d3m_options()
     _lib.d3m_default_options(C.byref(opt))
     opt.host_only = int(host_only)
@@ -177,6 +181,7 @@ def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol
     opt.use_graph = int(use_graph)
     opt.pivot_fallback = int(bool(pivot_fallback))
     opt.growth_limit_log10 = int(growth_limit_log10)
+    opt.k_multifrontal = int(bool(multifrontal))
     return opt
 
 
@@ -402,7 +407,7 @@ class Solver:
     def query(self):
         inf = d3m_info()
         _check(_lib.d3m_query(self._handle, C.byref(inf)))
-        return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name != "reserved"}
+        return {name: getattr(inf, name) for name, _ in d3m_info._fields_ if name not in ("reserved", "pad0")}
 
     def set_graphs(self, use_graph):
         """Replay captured HIP graphs (True) or launch eagerly (False) from now on."""

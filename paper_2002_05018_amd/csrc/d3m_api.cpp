@@ -81,6 +81,8 @@ struct d3m_problem {
     int64_t *d_split = nullptr, *d_collect = nullptr, *d_hmap = nullptr, *d_lmap = nullptr;
     int64_t *d_copymap = nullptr;
     int64_t *d_sq_fwd = nullptr, *d_sq_bwd = nullptr;
+    AddTask *d_mfadd = nullptr;
+    int64_t *d_mfsrc = nullptr;
     unsigned long long *d_disc = nullptr;
     FactorTile *d_lhat_s1 = nullptr, *d_lhat_k = nullptr;
     unsigned long long *d_growth = nullptr;
@@ -311,6 +313,8 @@ int upload_schedules(d3m_problem *h, bool replace) {
     UPS(h->d_lhat_k, pl.lhat_k);
     UPS(h->d_hmap, pl.h_map);
     UPS(h->d_lmap, pl.lam_map);
+    UPS(h->d_mfadd, pl.mf_add);
+    UPS(h->d_mfsrc, pl.mf_src);
 #undef UPS
     return D3M_OK;
 }
@@ -384,7 +388,8 @@ int ensure_arrays(d3m_problem *h) {
     const int pr = std::is_same<T, double>::value ? 0 : 1;
     const size_t es = sizeof(T) * 2;
     const Plan &pl = h->pl;
-    const i64 tiles[ARR_COUNT] = {pl.m_tiles, pl.m_tiles, pl.k_tiles, pl.k_tiles, pl.k_tiles, pl.tt_tiles};
+    const i64 tiles[ARR_COUNT] = {pl.m_tiles, pl.m_tiles, pl.k_tiles, pl.k_tiles,
+                                  pl.k_tiles, pl.tt_tiles, pl.mf ? pl.ku_tiles : 0};
     for (int a = 0; a < ARR_COUNT; ++a) {
         int rc = h->ensure(h->arr[pr][a], (size_t)tiles[a] * TILE_ELEMS * es);
         if (rc != D3M_OK) return rc;
@@ -617,6 +622,44 @@ int run_factor_sweep(d3m_problem *h, const std::vector<FactorStep> &steps, const
     return D3M_OK;
 }
 
+// Step 5 in multifrontal form, one elimination-tree level per step on s:
+// the extend-adds of the level's fronts, the pivot and panel launches, then
+// the update GEMMs into the level's update matrices.
+template <typename T>
+int run_multifrontal_sweep(d3m_problem *h, const Bases &b, hipStream_t s) {
+    for (const auto &st : h->pl.mf_steps) {
+        hipEvent_t ev{};
+        if (st.nadd > 0) {
+            h->prof_begin(KID_ASM, ev, s);
+            HIPCHK(launch_extend_add<T>(h->d_mfadd + st.add0, st.nadd, h->d_mfsrc, b, s));
+            h->prof_end(KID_ASM, ev, 0.0, s);
+        }
+        if (st.nbk > 0) {
+            h->prof_begin(KID_BK, ev, s);
+            HIPCHK(launch_bk<T>(h->d_bk + st.bk0, st.nbk, st.bk_maxn, h->d_pairs, b, h->D, h->d_status,
+                                h->d_bkscratch, s));
+            h->prof_end(KID_BK, ev, 0.0, s);
+        }
+        if (st.npan > 0 || st.nsc > 0) {
+            h->prof_begin(KID_PANEL, ev, s);
+            if (st.fused_scale) {
+                HIPCHK(launch_panel_scale<T>(h->d_gemm + st.pan0, h->d_scale + st.sc0, st.npan, h->d_pairs, b, h->D,
+                                             h->tune.panel_rows == 16 ? 16 : 64, s));
+            } else {
+                HIPCHK(launch_gemm<T>(h->d_gemm + st.pan0, st.npan, h->d_pairs, b, 0, s));
+                HIPCHK(launch_scale<T>(h->d_scale + st.sc0, st.nsc, b, h->D, s));
+            }
+            h->prof_end(KID_PANEL, ev, st.pan_flops, s);
+        }
+        if (st.nup > 0) {
+            h->prof_begin(KID_UPDATE, ev, s);
+            HIPCHK(launch_gemm<T>(h->d_gemm + st.up0, st.nup, h->d_pairs, b, 1, s));
+            h->prof_end(KID_UPDATE, ev, st.up_flops, s);
+        }
+    }
+    return D3M_OK;
+}
+
 // Captures the launches body(gstream) makes into g (nothing runs).
 template <typename F>
 int capture_graph(d3m_problem *h, d3m_problem::Graph &g, F &&body) {
@@ -668,6 +711,7 @@ int factor_launch(d3m_problem *h, hipStream_t s) {
     h->prof_begin(KID_ASM, ev, s);
     HIPCHK(launch_asm<T>(h->d_asm, (int64_t)pl.asmb.size(), b, s));
     h->prof_end(KID_ASM, ev, 0.0, s);
+    if (pl.mf) return run_multifrontal_sweep<T>(h, b, s);
     return run_factor_sweep<T>(h, pl.k_steps, b, s);
 }
 
@@ -990,6 +1034,13 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
     return D3M_OK;
 }
 
+// The plan of a handle: build_plan, then the multifrontal schedule of step 5
+// when the handle's options ask for it.
+void make_plan(Plan &pl, const d3m_problem *h, int scope, int s1_block, int k_block, bool k_fuse) {
+    build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse);
+    if (h->opt.k_multifrontal) build_multifrontal(pl, k_block > 0 ? k_block : 2);
+}
+
 // Re-plans the handle for another pivot scope of step 5 (0: pieces of at most
 // 64 rows, 1: whole blocks as in Algorithm 1).  The units, and with them the
 // schedules, the pivot data of K and its storage, change; the factors are
@@ -997,7 +1048,7 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
 int replan_scope(d3m_problem *h, int scope) {
     Plan np;
     try {
-        build_plan(np, h->dc, h->bo, scope == 1 ? 0 : TILE, h->tune.s1_block, h->tune.k_block, h->tune.k_fuse != 0);
+        make_plan(np, h, scope, h->tune.s1_block, h->tune.k_block, h->tune.k_fuse != 0);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {
@@ -1039,6 +1090,9 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
     if (h->opt.quad_points <= 0) h->opt.quad_points = 12;
     if (h->opt.ir_max_iter <= 0 && !opt) h->opt.ir_max_iter = 10;
     if (!(h->opt.ir_tol > 0)) h->opt.ir_tol = 1e-10;
+    if (h->opt.pivot_scope != 0 && h->opt.pivot_scope != 1) return fail(D3M_EINVAL, "pivot_scope must be 0 or 1");
+    if (h->opt.k_multifrontal != 0 && h->opt.k_multifrontal != 1)
+        return fail(D3M_EINVAL, "k_multifrontal must be 0 or 1");
     try {
         build_mesh(h->mesh, nv, xyz, nt, tets);
         h->k = k;
@@ -1048,7 +1102,7 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
         if (!sub_group.empty() && (int)sub_group.size() != h->dc.N)
             throw Error{-1, "a problem of the batch has an empty subdomain"};
         order_blocks(h->bo, h->dc, h->mesh, sub_group);
-        build_plan(h->pl, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, h->opt.s1_block, 0, false);
+        make_plan(h->pl, h.get(), h->opt.pivot_scope, h->opt.s1_block, 0, false);
     } catch (const Error &e) {
         return fail(D3M_EINVAL, e.msg);
     } catch (const std::bad_alloc &) {
@@ -1139,10 +1193,12 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     h->drop_graphs();
     h->tune = *t;
     if (t->s1_block != old_s1 || t->k_block != old_k || t->k_fuse != old_f) {
-        // the tile layout does not depend on the blocking: only the schedules change
+        // the tile layout does not depend on the blocking: only the schedules
+        // change (and the size of the multifrontal update-matrix pool, which
+        // the next factorisation allocates)
         Plan np;
         try {
-            build_plan(np, h->dc, h->bo, h->opt.pivot_scope == 1 ? 0 : TILE, t->s1_block, t->k_block, t->k_fuse != 0);
+            make_plan(np, h, h->opt.pivot_scope, t->s1_block, t->k_block, t->k_fuse != 0);
         } catch (const Error &e) {
             return fail(D3M_EINVAL, e.msg);
         } catch (const std::bad_alloc &) {
@@ -1476,6 +1532,13 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->pivot_scope = h->opt.pivot_scope;
     info->pivot_fallbacks = h->pivot_fallbacks;
     info->solve_vector_bytes = (double)h->pl.solve_min_vblocks * TILE * 16.0;
+    info->k_multifrontal = h->pl.mf ? 1 : 0;
+    if (h->pl.mf) {
+        info->mf_pool_bytes = (double)h->pl.ku_tiles * TILE_ELEMS * 16.0;
+        info->mf_update_bytes = (double)h->pl.ku_tiles_total * TILE_ELEMS * 16.0;
+        info->mf_extend_add_bytes = h->pl.mf_add_bytes;
+        info->array_bytes += h->pl.ku_tiles * (int64_t)TILE_ELEMS * 16;
+    }
     return D3M_OK;
 }
 

@@ -29,6 +29,7 @@ struct FactorStep {
     // between the streams (a launch waits only for earlier launches that
     // wrote its columns)
     bool track = false;
+    i64 add0 = 0, nadd = 0;  // multifrontal form: extend-add tasks run before the pivot launch
     i64 nnear = 0;
     double near_flops = 0.0;
     std::vector<int> cols_bk, cols_crit, cols_near, cols_far;
@@ -98,6 +99,20 @@ struct Plan {
     std::vector<int64_t> h_map;        // per K vector row: the two subdomain vector rows (-1: padding)
     std::vector<int64_t> lam_map;      // per S1 vector row: K vector row of a multiplier row, else -1
     std::vector<int64_t> lm_vrow;      // per global multiplier: its K vector row
+    // ---- multifrontal form of step 5 (built on request) --------------------
+    // Same units, pivot, panel and factor storage as the right-looking
+    // schedule; the Schur updates beyond a front (a chain segment of units)
+    // go to its update matrix (a packed lower tile triangle over the tile
+    // rows of the last unit's struct, in the ARR_KU pool, indexed by the
+    // segment's first unit), which the parent's step adds into its front.
+    bool mf = false;
+    std::vector<FactorStep> mf_steps;
+    std::vector<AddTask> mf_add;
+    std::vector<int64_t> mf_src;
+    std::vector<i64> mf_ubase;         // pool slot of U_s by first unit s (-1: none)
+    i64 ku_tiles = 0;                  // tiles of the update-matrix pool
+    i64 ku_tiles_total = 0;            // ... without reuse (sum over units)
+    double mf_add_bytes = 0.0;         // complex128 bytes moved by the extend-adds of one factorisation
     // ---- algorithmic counts -----------------------------------------------
     double flops_s1 = 0.0, flops_s3 = 0.0, flops_update = 0.0;
     double mfma_flops_update = 0.0;    // update-GEMM work as executed on full 64x64x64 tile
@@ -111,5 +126,10 @@ struct Plan {
 
 void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
                 bool k_fuse);
+
+// Adds the multifrontal schedule of step 5 to a plan made by build_plan;
+// fronts are amalgamated along elimination-tree chains of at most seg_max
+// units (1: one front per unit).
+void build_multifrontal(Plan &pl, int seg_max);
 
 }  // namespace d3m

@@ -959,6 +959,28 @@ __global__ void asm_kernel(const AsmTask *tasks, Bases bases) {
     }
 }
 
+// Extend-add of the multifrontal form: one work-group per destination tile,
+// dst (= or +=) the sum of its source tiles (whole 64 x 64 tiles; the sum is
+// formed in FP64 and rounded once).  Each thread handles 16 consecutive
+// complex entries of a tile; the source list of the task is read into a
+// register of each lane first.
+template <typename T2>
+__global__ __launch_bounds__(256) void extend_add_kernel(const AddTask *tasks, const int64_t *srcs, Bases bases) {
+    const AddTask tk = tasks[blockIdx.x];
+    T2 *dst = enc_ptr<T2>(bases, tk.dst);
+    double2 acc[16];
+    const int e0 = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = tk.accumulate ? to_d2(dst[e0 + 256 * q]) : make_double2(0.0, 0.0);
+    for (int x = 0; x < tk.ns; ++x) {
+        const T2 *src = enc_ptr<T2>(bases, srcs[tk.s0 + x]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = cadd(acc[q], to_d2(src[e0 + 256 * q]));
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dst[e0 + 256 * q] = from_d2<T2>(acc[q]);
+}
+
 // ------------------------------------------------------------ launchers --
 namespace {
 inline unsigned grid_for(int64_t n, int block) {
@@ -1110,6 +1132,16 @@ hipError_t launch_scale(const ScaleTask *tasks, int64_t ntask, const Bases &b, c
 }
 
 template <typename T>
+hipError_t launch_extend_add(const AddTask *tasks, int64_t ntask, const int64_t *srcs, const Bases &b,
+                             hipStream_t s) {
+    using T2 = typename C2T<T>::type;
+    if (ntask <= 0) return hipSuccess;
+    if (ntask > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(extend_add_kernel<T2>, dim3((unsigned)ntask), dim3(256), 0, s, tasks, srcs, b);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipStream_t s) {
     using T2 = typename C2T<T>::type;
     if (ntask <= 0) return hipSuccess;
@@ -1129,6 +1161,8 @@ hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipSt
                                               const Bases &, const DArrays &, int, hipStream_t);              \
     template hipError_t launch_scale<T>(const ScaleTask *, int64_t, const Bases &, const DArrays &,            \
                                         hipStream_t);                                                         \
+    template hipError_t launch_extend_add<T>(const AddTask *, int64_t, const int64_t *, const Bases &,          \
+                                             hipStream_t);                                                    \
     template hipError_t launch_asm<T>(const AsmTask *, int64_t, const Bases &, hipStream_t);                    \
     template hipError_t launch_growth<T>(const FactorTile *, int64_t, const Bases &, unsigned long long *,       \
                                          hipStream_t);

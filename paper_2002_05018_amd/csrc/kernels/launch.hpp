@@ -42,6 +42,10 @@ template <typename T>
 hipError_t launch_panel_scale(const GemmTask *tasks, const ScaleTask *stasks, int64_t ntask, const GemmPair *pairs,
                               const Bases &b, const DArrays &D, int rows, hipStream_t s);
 template <typename T> hipError_t launch_asm(const AsmTask *tasks, int64_t ntask, const Bases &b, hipStream_t s);
+// multifrontal extend-adds: one work-group per destination tile
+template <typename T>
+hipError_t launch_extend_add(const AddTask *tasks, int64_t ntask, const int64_t *srcs, const Bases &b,
+                             hipStream_t s);
 // max |entry| over the valid part of the given factor tiles, folded into
 // *gmax (bit pattern of a non-negative double; zeroed by the caller)
 template <typename T>

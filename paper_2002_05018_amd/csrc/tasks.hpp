@@ -16,7 +16,8 @@ enum Arr : int {
     ARR_KX = 3,  // panel products of the K blocks
     ARR_KL = 4,  // factor tiles of -K (unit lower L_jj and L_ij)
     ARR_TT = 5,  // L_jj^{-1} P_j^T of every diagonal block
-    ARR_COUNT = 6
+    ARR_KU = 6,  // update matrices of the multifrontal form of step 5
+    ARR_COUNT = 7
 };
 
 constexpr int64_t TILE_ELEMS_D = 4096;  // complex elements of a 64 x 64 tile
@@ -61,6 +62,17 @@ struct ScaleTask {
     int32_t ncols;
     int32_t nq;            // pending updates of the panel's input tile (fused panel only):
     int32_t q0, pad;       //   pairs (X, W) q0 .. q0 + nq - 1, applied before the product
+};
+
+// Extend-add of the multifrontal form: dst (= or +=) the sum of source
+// tiles srcs[s0 .. s0 + ns - 1] (encoded tile offsets).  A child's update
+// matrix tile and its place in the parent's front cover the same rows and
+// columns, so whole tiles are added.
+struct AddTask {
+    int64_t dst;
+    int32_t s0, ns;
+    int32_t accumulate;  // 1: dst += sum, 0: dst = sum (zero when ns == 0)
+    int32_t pad;
 };
 
 // Assembly of one tile of the LM Schur complement from <= 2 subdomains

@@ -55,12 +55,12 @@ def _check(s, fx, E, label, tol):
     print(msg, flush=True)
 
 
-def _run(cfg, precisions=("fp64", "fp32_ir")):
+def _run(cfg, precisions=("fp64", "fp32_ir"), **solver_kw):
     from paper_2002_05018_amd import Solver
     fx = load_fixture(cfg)
     prob = W.make_config(cfg)
-    print(f"[parity] configuration {cfg}", flush=True)
-    s = Solver.from_problem(prob)
+    print(f"[parity] configuration {cfg} {solver_kw}", flush=True)
+    s = Solver.from_problem(prob, **solver_kw)
     f = s.rhs_planewave(prob.dirs, prob.pols)
     assert_rhs_close(f[:, fx["edges"]], fx["f"], 1e-13, "plane-wave load")
     S, fo = _oracle_system(prob)
@@ -89,6 +89,15 @@ def test_config4_against_oracle():
 
 def test_config5_against_oracle():
     _run(5, precisions=("fp64",))
+
+
+def test_config2_multifrontal_against_oracle():
+    """Step 5 in its multifrontal form (update matrices and extend-adds)."""
+    _run(2, multifrontal=True)
+
+
+def test_config4_multifrontal_against_oracle():
+    _run(4, precisions=("fp64",), multifrontal=True)
 
 
 def test_config3_batch_against_oracle():
