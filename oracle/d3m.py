@@ -30,9 +30,9 @@ class D3MOracle:
     """Reference D3M solver for a ``workloads.Problem``-like set of arrays."""
 
     def __init__(self, xyz, tets, part, eps_r, k, alpha, parts=None, order=None,
-                 pivoting=True, multifrontal=False):
+                 pivoting=True, multifrontal=False, pec_faces=None):
         t0 = time.perf_counter()
-        self.fem = GlobalFEM(xyz, tets, eps_r, k)
+        self.fem = GlobalFEM(xyz, tets, eps_r, k, pec_faces=pec_faces)
         self.dec = Decomposition(self.fem, part, alpha)
         self.parts = parts
         self.pivoting = pivoting
@@ -42,8 +42,9 @@ class D3MOracle:
 
     @classmethod
     def from_problem(cls, prob, **kw):
+        pec = getattr(prob, "pec_faces", None)
         return cls(prob.xyz, prob.tets, prob.part, prob.eps_r, prob.k, prob.alpha,
-                   parts=prob.parts, **kw)
+                   parts=prob.parts, pec_faces=pec, **kw)
 
     # steps 1-5
     def factor(self):
@@ -117,9 +118,13 @@ def adjoint_gradient(fem: GlobalFEM, w, E):
 
 
 def global_solve(fem: GlobalFEM, f):
-    """The plain definition E = S^{-1} f by sparse LU of the undecomposed S."""
-    lu = sla.splu(fem.S.tocsc())
-    return lu.solve(np.atleast_2d(f).T.copy()).T
+    """The plain definition E = S^{-1} f by sparse LU of the undecomposed S
+    (on the unknowns; zero on PEC edges)."""
+    f = np.atleast_2d(f)
+    E = np.zeros(f.shape, dtype=np.complex128)
+    lu = sla.splu(fem.system().tocsc())
+    E[:, fem.free] = lu.solve(f[:, fem.free].T.copy()).T
+    return E
 
 
 def relative_residual(S, E, f):

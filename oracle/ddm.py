@@ -19,6 +19,9 @@ Readings of the paper used here (each is listed in the design notes):
 * The sum in eq. (1) runs over subdomains: K = sum_d D_d^T A_d^{-1} D_d and
   g = sum_d D_d^T A_d^{-1} f_d (from A E + D lambda = f, D^T E = 0).
 * A global load f is split with f_d[e] = f[e] for d = min Sub(e), else 0.
+* Edges on PEC triangles are not unknowns: they belong to no subdomain
+  system and carry no multipliers (the continuity of a field fixed to zero
+  needs no constraint).
 """
 from __future__ import annotations
 
@@ -60,16 +63,18 @@ class Decomposition:
         if np.any(np.bincount(self.part, minlength=N) == 0):
             raise ValueError("empty subdomain")
 
-        # Sub(e): subdomains containing each edge
+        # Sub(e): subdomains containing each unknown (non-PEC) edge
         pe = np.unique(np.stack([np.repeat(self.part, 6), topo.tet_edges.ravel()], 1), axis=0)
         self.sub_of_edge = [[] for _ in range(topo.n_edges)]
         for d, e in pe:
-            self.sub_of_edge[e].append(int(d))
-        self.owner = np.array([s[0] for s in self.sub_of_edge], dtype=np.int64)
-        # local numbering: sorted global edge ids of each subdomain
+            if not fem.pec[e]:
+                self.sub_of_edge[e].append(int(d))
+        self.owner = np.array([s[0] if s else -1 for s in self.sub_of_edge], dtype=np.int64)
+        # local numbering: sorted global ids of each subdomain's unknown edges
         self.sub_edges = []
         for d in range(N):
-            self.sub_edges.append(np.unique(topo.tet_edges[self.part == d].ravel()))
+            ge = np.unique(topo.tet_edges[self.part == d].ravel())
+            self.sub_edges.append(ge[~fem.pec[ge]])
 
         # interface triangles: faces whose two tetrahedra lie in different parts
         two = np.nonzero(topo.face_count == 2)[0]
@@ -93,7 +98,7 @@ class Decomposition:
                 cand.setdefault(int(e), set()).add((int(p), int(q)))
         lms = []
         for e, subs in enumerate(self.sub_of_edge):
-            if len(subs) < 2:
+            if len(subs) < 2:  # interior, or a PEC edge (no subdomain holds it)
                 continue
             dsu = _DSU(subs)
             chosen = []
@@ -123,25 +128,28 @@ class Decomposition:
         for d in range(self.N):
             ge = self.sub_edges[d]
             nd = ge.size
+            locmap = np.full(topo.n_edges, -1, dtype=np.int64)  # -1: not an unknown of d
+            locmap[ge] = np.arange(nd)
             loc = {int(e): i for i, e in enumerate(ge)}
             rows, cols, vals = [], [], []
             tl = np.nonzero(self.part == d)[0]
-            te = np.vectorize(loc.get)(topo.tet_edges[tl]) if tl.size else np.zeros((0, 6), int)
+            te = locmap[topo.tet_edges[tl]]
             rows.append(np.repeat(te, 6, 1).ravel()); cols.append(np.tile(te, (1, 6)).ravel())
             vals.append(fem.Se[tl].astype(np.complex128).ravel())
             bsel = np.nonzero(self.part[bf_tet] == d)[0]
             if bsel.size:
-                fe = np.vectorize(loc.get)(topo.face_edges[fem.bfaces[bsel]])
+                fe = locmap[topo.face_edges[fem.bfaces[bsel]]]
                 rows.append(np.repeat(fe, 3, 1).ravel()); cols.append(np.tile(fe, (1, 3)).ravel())
                 vals.append((1j * fem.k * fem.Tb[bsel]).ravel())
             for sign, col in ((+1.0, 0), (-1.0, 1)):
                 isel = np.nonzero(self.iface_pq[:, col] == d)[0]
                 if isel.size:
-                    fe = np.vectorize(loc.get)(topo.face_edges[self.iface[isel]])
+                    fe = locmap[topo.face_edges[self.iface[isel]]]
                     rows.append(np.repeat(fe, 3, 1).ravel()); cols.append(np.tile(fe, (1, 3)).ravel())
                     vals.append((sign * self.alpha * self.Ti[isel]).ravel())
-            A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                              shape=(nd, nd)).tocsc()
+            r_, c_, v_ = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+            keep = (r_ >= 0) & (c_ >= 0)  # entries of PEC rows or columns leave the system
+            A = sp.coo_matrix((v_[keep], (r_[keep], c_[keep])), shape=(nd, nd)).tocsc()
             A.sum_duplicates()
             self.A.append(A)
             # D_d restricted to the LMs touching d (sorted by global LM index)
@@ -165,7 +173,7 @@ class Decomposition:
         return out
 
     def sum_subdomain_matrices(self):
-        """sum_d R_d^T A_d R_d (equals S: the Robin terms cancel)."""
+        """sum_d R_d^T A_d R_d (equals S on the unknowns: the Robin terms cancel)."""
         n = self.fem.topo.n_edges
         tot = sp.csr_matrix((n, n), dtype=np.complex128)
         for d in range(self.N):

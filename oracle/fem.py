@@ -1,10 +1,16 @@
 """Lowest-order Nedelec (Whitney) FEM of the BVP in Section II -- oracle.
 
-BVP (Section II, first two lines of the decomposed problem, mu_r = 1,
-J_imp = 0):
+BVP (Section II, first two lines of the decomposed problem, mu_r = 1):
 
-    curl curl E - k^2 eps_r E = 0                       in the cube
+    curl curl E - k^2 eps_r E = -jk eta J_imp           in the cube
     n x curl E - jk E_t = n x curl E_inc - jk E_inc,t   on its boundary
+    n x E = 0                                           on PEC surfaces
+
+PEC surfaces are given as mesh triangles; every edge of such a triangle has
+a zero tangential field and is eliminated (its row and column leave the
+system, E = 0 there).  The impressed current is a point dipole J_imp =
+m delta(r - r0) (current moment m = I l, in A m), whose load on edge e is
+-jk eta m . N_e(r0), with eta the free-space impedance.
 
 Time convention e^{+j omega t}; the incident plane wave is
 E_inc = p exp(-jk d.r).  Multiplying by a test function v, integrating by
@@ -25,6 +31,8 @@ import numpy as np
 import scipy.sparse as sp
 
 from .quad import triangle_rule
+
+ETA0 = 376.730313668  # free-space wave impedance, ohm (CODATA 2018)
 
 TET_EDGES = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
 TET_FACES = [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]
@@ -203,11 +211,26 @@ def edge_interpolant(xyz, edges, k, d, p):
 
 
 class GlobalFEM:
-    """Undecomposed FEM system S (CSR, complex symmetric) and plane-wave loads."""
+    """Undecomposed FEM system S (CSR, complex symmetric), plane-wave and
+    dipole loads.  ``S`` holds every edge; the unknowns are the edges not on
+    a PEC triangle (``free``), and the system is S[free, free]."""
 
-    def __init__(self, xyz, tets, eps_r, k):
+    def __init__(self, xyz, tets, eps_r, k, pec_faces=None):
         self.topo = Topology(xyz, tets)
         t = self.topo
+        self.pec = np.zeros(t.n_edges, dtype=bool)
+        if pec_faces is not None and len(pec_faces):
+            nv = t.n_vertices
+            fk = np.sort(np.asarray(pec_faces, dtype=np.int64), axis=1)
+            keys = (fk[:, 0] * nv + fk[:, 1]) * nv + fk[:, 2]
+            have = (t.faces[:, 0] * nv + t.faces[:, 1]) * nv + t.faces[:, 2]
+            order = np.argsort(have)
+            pos = np.searchsorted(have[order], keys)
+            pos = np.minimum(pos, have.size - 1)
+            if np.any(have[order][pos] != keys):
+                raise ValueError("a PEC triangle is not a face of the mesh")
+            self.pec[t.face_edges[order[pos]].ravel()] = True
+        self.free = np.nonzero(~self.pec)[0]
         self.k = float(k)
         self.eps_r = np.asarray(eps_r, dtype=np.float64)
         self.G, self.V = tet_geometry(t.xyz, t.tets)
@@ -250,7 +273,29 @@ class GlobalFEM:
             loc = planewave_face_load(t.xyz, t.faces[self.bfaces], self.bnormals,
                                       self.k, dirs[r], pols[r], q)
             np.add.at(f[r], fe.ravel(), loc.ravel())
+        f[:, self.pec] = 0.0
         return f
+
+    def dipole_rhs(self, pos, moment):
+        """f [nrhs, n_edges] for point dipoles J_imp = m delta(r - r0), one per
+        right-hand side: f_e = -jk eta m . N_e(r0) (zero on PEC edges)."""
+        pos = np.atleast_2d(pos)
+        moment = np.atleast_2d(np.asarray(moment, dtype=np.complex128))
+        P = probe_matrix(self.topo, pos)  # [nrhs, 3, n_edges]
+        f = -1j * self.k * ETA0 * np.einsum("rx,rxe->re", moment, P)
+        f[:, self.pec] = 0.0
+        return f
+
+    def system(self):
+        """S restricted to the unknowns (rows and columns of non-PEC edges)."""
+        return self.S[self.free][:, self.free]
+
+    def relative_residual(self, E, f):
+        """max over right-hand sides of ||(S E - f)[free]||_inf / ||f[free]||_inf."""
+        E = np.atleast_2d(E)
+        f = np.atleast_2d(f)
+        r = (self.system() @ E[:, self.free].T).T - f[:, self.free]
+        return float(np.max(np.abs(r).max(axis=1) / np.abs(f[:, self.free]).max(axis=1)))
 
     def unit_mass(self):
         """Per-tetrahedron unit-eps_r mass matrices (for dS/d eps_r = -k^2 M)."""

@@ -27,6 +27,9 @@ __all__ = [
     "make_problem",
     "make_config",
     "make_batch_config",
+    "make_pec_config",
+    "plate_faces",
+    "box_shell_faces",
     "CONFIGS",
 ]
 
@@ -90,6 +93,48 @@ def box_partition(n: int, parts=(1, 1, 1), cuts=None):
     return np.repeat(hex_part, 6)
 
 
+def plate_faces(n: int, tets, axis: int, level: int, lo, hi):
+    """Triangles of the Kuhn mesh lying in the plane x_axis = level / n inside
+    the rectangle lo <= (other two coordinates) * n <= hi (hex units, lo and
+    hi pairs for the two remaining axes in increasing axis order).  Returned
+    as vertex-id triples [nf, 3], each triangle once."""
+    m = n + 1
+    ijk = lambda v: np.stack([v // (m * m), (v // m) % m, v % m], axis=-1)
+    faces = np.concatenate([tets[:, [0, 1, 2]], tets[:, [0, 1, 3]], tets[:, [0, 2, 3]], tets[:, [1, 2, 3]]])
+    c = ijk(faces)  # [nf, 3 vertices, 3 axes]
+    others = [a for a in range(3) if a != axis]
+    on = np.all(c[:, :, axis] == level, axis=1)
+    for o, a in enumerate(others):
+        on &= np.all((c[:, :, a] >= lo[o]) & (c[:, :, a] <= hi[o]), axis=1)
+    return np.unique(np.sort(faces[on], axis=1), axis=0)
+
+
+def box_shell_faces(n: int, tets, lo, hi):
+    """Triangles on the six sides of the box lo <= x, y, z <= hi (hex units)."""
+    out = []
+    for axis in range(3):
+        o = [a for a in range(3) if a != axis]
+        for level in (lo[axis], hi[axis]):
+            out.append(plate_faces(n, tets, axis, level, [lo[o[0]], lo[o[1]]], [hi[o[0]], hi[o[1]]]))
+    return np.unique(np.concatenate(out), axis=0)
+
+
+def _draw_dipoles(rng, count, keep_out=None):
+    """Dipole positions uniform in [0.1, 0.9]^3 (redrawn while keep_out(pos) is
+    true) and unit current moments with a uniform random phase."""
+    pos = np.empty((count, 3))
+    for i in range(count):
+        while True:
+            r = rng.uniform(0.1, 0.9, 3)
+            if keep_out is None or not keep_out(r):
+                break
+        pos[i] = r
+    u = rng.standard_normal((count, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    phase = np.exp(1j * rng.uniform(0.0, 2.0 * math.pi, count))
+    return pos, u * phase[:, None]
+
+
 def _tet_centroids(xyz, tets):
     return xyz[tets].mean(axis=1)
 
@@ -123,6 +168,11 @@ class Problem:
     fd_tets: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int64))
     fd_h: float = 1e-6
     precision: str = "fp64"
+    # PEC triangles (vertex-id triples) and point-dipole sources (one
+    # right-hand side each, after the plane waves): position, current moment
+    pec_faces: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), dtype=np.int64))
+    dip_pos: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    dip_moment: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), dtype=np.complex128))
 
     @property
     def nrhs(self) -> int:
@@ -222,6 +272,32 @@ def make_config(i: int, seed: int | None = None) -> Problem:
     if i == 3:
         raise ValueError("configuration 3 is a batch; use make_batch_config()")
     raise ValueError(f"unknown configuration {i}")
+
+
+def make_pec_config(seed: int = 6, n: int = 24, parts=(4, 4, 4), n_pw: int = 4, n_dip: int = 4) -> Problem:
+    """PEC plates and impressed currents (the second workload of the paper's
+    BVP: perfectly conducting scatterers, J_imp sources).  The paper's
+    plate meshes are not given; this cube stands in: n^3 hexes in box
+    subdomains, free space (eps_r = 1), k = 6*pi (wavelength 1/3, eight hexes
+    per wavelength at n = 24), two square PEC plates -- one in the plane
+    z = 1/2 (a subdomain interface for 4x4x4 boxes) over 1/4 <= x, y <= 3/4
+    (1.5 wavelengths), one in the plane x = 3/8 (inside a subdomain) over
+    1/8 <= y, z <= 3/8 -- and n_pw plane waves followed by n_dip point dipoles
+    (kept more than 1/12 away from the plates' planes).  Draw order: plane
+    waves, then dipoles."""
+    rng = np.random.default_rng(seed)
+    xyz, tets = kuhn_cube_mesh(n)
+    k = 6 * math.pi
+    q = n // 8
+    pec = np.unique(np.concatenate([
+        plate_faces(n, tets, 2, 4 * q, [2 * q, 2 * q], [6 * q, 6 * q]),
+        plate_faces(n, tets, 0, 3 * q, [q, q], [3 * q, 3 * q])]), axis=0)
+    dirs, pols = _draw_plane_waves(rng, n_pw)
+    far = 1.0 / 12
+    keep_out = lambda r: abs(r[2] - 0.5) < far or abs(r[0] - 0.375) < far
+    dpos, dmom = _draw_dipoles(rng, n_dip, keep_out)
+    return Problem("pec_plates", n, tuple(parts), xyz, tets, box_partition(n, parts), np.ones(tets.shape[0]),
+                   k, -1j * k, dirs, pols, pec_faces=pec, dip_pos=dpos, dip_moment=dmom)
 
 
 def make_batch_config(seed: int = 3, count: int = 32, n_range=(12, 32), nrhs=16, hex_size=0.125):
