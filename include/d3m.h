@@ -61,13 +61,25 @@ typedef struct d3m_problem *d3m_handle;
 
 /* Tetrahedral mesh.  xyz: [n_vertices][3] row-major; tets: [n_tets][4],
  * 0-based vertex ids (any vertex order; the library sorts each tetrahedron so
- * every local edge points from the lower to the higher global vertex id). */
+ * every local edge points from the lower to the higher global vertex id).
+ * pec_faces: [n_pec_faces][3] vertex ids of mesh triangles on perfectly
+ * conducting surfaces (n x E = 0, the PEC scatterers of Section III), or
+ * NULL with n_pec_faces = 0.  Every edge of such a triangle has a zero
+ * tangential field: it is no unknown of any subdomain system and carries no
+ * multiplier; E is 0 there and loads on it are ignored.  A triple that is not
+ * a face of the mesh is refused (D3M_EINVAL). */
 typedef struct {
     int64_t n_vertices;
     const double *xyz;
     int64_t n_tets;
     const int64_t *tets;
+    int64_t n_pec_faces;
+    const int64_t *pec_faces;
 } d3m_mesh;
+
+/* Free-space wave impedance (ohm) of the impressed-current term -jk eta J_imp
+ * of the BVP (Section II, first line). */
+#define D3M_ETA0 376.730313668
 
 typedef struct {
     int32_t host_only;    /* 1: d3m_setup stops before any HIP call; only the
@@ -311,6 +323,15 @@ int d3m_rhs_planewave(d3m_handle h, const double *dirs, const double *pols,
  *   dirs, pols [count][nrhs][3]; f [nrhs][n_edges] host output. */
 int d3m_rhs_planewave_batch(d3m_handle h, const double *dirs,
                             const double *pols, int32_t nrhs, d3m_c128 *f);
+
+/* Loads of point dipoles (the impressed current J_imp of the BVP in Section
+ * II, first line), one per right-hand side: J_imp = m_c delta(r - r_c) with
+ * position pos[c] ([nrhs][3]) and complex current moment m_c = moment[c]
+ * ([nrhs][3], I l in A m), giving f[c][e] = -jk eta0 m_c . N_e(r_c) (N_e the
+ * Whitney function of edge e in the tetrahedron holding r_c; zero on PEC
+ * edges).  f: host buffer [nrhs][n_edges], overwritten.  Single-problem
+ * handles only; D3M_EINVAL for a point outside the mesh. */
+int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int32_t nrhs, d3m_c128 *f);
 
 /* Whitney field evaluation at points: for point m, E(r_m) = sum_a c[m][a][:] *
  * u[edge[m][a]] over the six edges of the tetrahedron containing r_m.

@@ -42,7 +42,7 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
                     "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth",
-                    "d3m_solve_noalloc"]
+                    "d3m_solve_noalloc", "d3m_rhs_dipole"]
 
 
 class d3m_c128(C.Structure):
@@ -51,7 +51,20 @@ class d3m_c128(C.Structure):
 
 class d3m_mesh(C.Structure):
     _fields_ = [("n_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)),
-                ("n_tets", C.c_int64), ("tets", C.POINTER(C.c_int64))]
+                ("n_tets", C.c_int64), ("tets", C.POINTER(C.c_int64)),
+                ("n_pec_faces", C.c_int64), ("pec_faces", C.POINTER(C.c_int64))]
+
+
+def _mesh(xyz, tets, pec_faces, keep):
+    """d3m_mesh over contiguous copies (kept alive in ``keep``)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int64)
+    pec = np.ascontiguousarray(np.zeros((0, 3)) if pec_faces is None else pec_faces, dtype=np.int64)
+    if pec.ndim != 2 or pec.shape[1] != 3:
+        raise ValueError("pec_faces must be [n][3] vertex ids")
+    keep += [xyz, tets, pec]
+    return d3m_mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int64),
+                    pec.shape[0], _ptr(pec, C.c_int64) if pec.shape[0] else None)
 
 
 class d3m_options(C.Structure):
@@ -117,6 +130,7 @@ _lib.d3m_solve.argtypes = [_h, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(d3m_
 _lib.d3m_adjoint.argtypes = [_h, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.d3m_rhs_planewave.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_void_p]
 _lib.d3m_probe.argtypes = [_h, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+_lib.d3m_rhs_dipole.argtypes = [_h, C.POINTER(C.c_double), C.c_void_p, C.c_int32, C.c_void_p]
 _lib.d3m_query.argtypes = [_h, C.POINTER(d3m_info)]
 _lib.d3m_destroy.argtypes = [_h]
 _lib.d3m_destroy.restype = None
@@ -133,7 +147,7 @@ _lib.d3m_factor_growth.restype = C.c_int
 _lib.d3m_solve_noalloc.argtypes = [_h, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
 _lib.d3m_solve_noalloc.restype = C.c_int
 for _f in ("d3m_setup", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch", "d3m_update_eps",
-           "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_probe", "d3m_query",
+           "d3m_factor", "d3m_solve", "d3m_adjoint", "d3m_rhs_planewave", "d3m_rhs_dipole", "d3m_probe", "d3m_query",
            "d3m_set_profile", "d3m_kernel_stats", "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs"):
     getattr(_lib, _f).restype = C.c_int
 
@@ -225,12 +239,11 @@ class Solver:
     """One decomposed problem, or a batch of independent ones, on the GPU (a
     d3m_handle)."""
 
-    def __init__(self, xyz, tets, part, eps_r, k, alpha, **kw):
-        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
-        tets = np.ascontiguousarray(tets, dtype=np.int64)
+    def __init__(self, xyz, tets, part, eps_r, k, alpha, pec_faces=None, **kw):
+        keep = []
         part = np.ascontiguousarray(part, dtype=np.int32)
         eps = np.ascontiguousarray(eps_r, dtype=np.float64)
-        mesh = d3m_mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int64))
+        mesh = _mesh(xyz, tets, pec_faces, keep)
         opt = _options(**kw)
         a = complex(alpha)
         h = _h()
@@ -245,12 +258,10 @@ class Solver:
         keep = []
         items = (d3m_batch_item * len(problems))()
         for i, p in enumerate(problems):
-            xyz = np.ascontiguousarray(p.xyz, dtype=np.float64)
-            tets = np.ascontiguousarray(p.tets, dtype=np.int64)
             part = np.ascontiguousarray(p.part, dtype=np.int32)
             eps = np.ascontiguousarray(p.eps_r, dtype=np.float64)
-            keep += [xyz, tets, part, eps]
-            items[i].mesh = d3m_mesh(xyz.shape[0], _ptr(xyz, C.c_double), tets.shape[0], _ptr(tets, C.c_int64))
+            keep += [part, eps]
+            items[i].mesh = _mesh(p.xyz, p.tets, getattr(p, "pec_faces", None), keep)
             items[i].part = _ptr(part, C.c_int32)
             items[i].eps_r = _ptr(eps, C.c_double)
         opt = _options(**kw)
@@ -276,7 +287,8 @@ class Solver:
 
     @classmethod
     def from_problem(cls, prob, **kw):
-        return cls(prob.xyz, prob.tets, prob.part, prob.eps_r, prob.k, prob.alpha, **kw)
+        return cls(prob.xyz, prob.tets, prob.part, prob.eps_r, prob.k, prob.alpha,
+                   pec_faces=getattr(prob, "pec_faces", None), **kw)
 
     def close(self):
         if getattr(self, "_handle", None):
@@ -365,6 +377,18 @@ class Solver:
         f = np.zeros((d.shape[0], self.n_edges), dtype=np.complex128)
         _check(_lib.d3m_rhs_planewave(self._handle, _ptr(d, C.c_double), _ptr(p, C.c_double), d.shape[0],
                                       C.c_void_p(f.ctypes.data)))
+        return f
+
+    def rhs_dipole(self, pos, moment):
+        """Point-dipole loads (impressed currents), one per right-hand side:
+        pos [nrhs][3], moment [nrhs][3] complex (current moment I l)."""
+        r = np.ascontiguousarray(np.atleast_2d(pos), dtype=np.float64)
+        m = np.ascontiguousarray(np.atleast_2d(moment), dtype=np.complex128)
+        if r.shape != m.shape or r.shape[1] != 3:
+            raise ValueError("pos and moment must both be [nrhs][3]")
+        f = np.zeros((r.shape[0], self.n_edges), dtype=np.complex128)
+        _check(_lib.d3m_rhs_dipole(self._handle, _ptr(r, C.c_double), C.c_void_p(m.ctypes.data), r.shape[0],
+                                   C.c_void_p(f.ctypes.data)))
         return f
 
     def rhs_planewave_batch(self, dirs, pols):

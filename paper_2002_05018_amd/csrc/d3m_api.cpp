@@ -252,20 +252,25 @@ namespace {
 
 void build_global_csr(const Mesh &m, const Decomp &dc, double k, const double *eps, std::vector<int64_t> &rowptr,
                       std::vector<int32_t> &col, std::vector<double2> &val) {
+    // rows and columns of PEC edges are left out (no unknowns; the residual
+    // kernel skips their rows)
     std::vector<std::vector<std::pair<int64_t, cplx>>> rows(m.ne);
+    auto keep = [&](i64 e) { return m.pec.empty() || !m.pec[e]; };
     double Kc[36], M[36], T[9];
     for (i64 t = 0; t < m.nt; ++t) {
         tet_curl_mass(m, t, Kc, M);
         for (int a = 0; a < 6; ++a)
             for (int b = 0; b < 6; ++b)
-                rows[m.tet_edges[6 * t + a]].push_back(
-                    {m.tet_edges[6 * t + b], cplx(Kc[6 * a + b] - k * k * eps[t] * M[6 * a + b], 0.0)});
+                if (keep(m.tet_edges[6 * t + a]) && keep(m.tet_edges[6 * t + b]))
+                    rows[m.tet_edges[6 * t + a]].push_back(
+                        {m.tet_edges[6 * t + b], cplx(Kc[6 * a + b] - k * k * eps[t] * M[6 * a + b], 0.0)});
     }
     for (i64 f : dc.bface) {
         tri_tangential_mass(m, f, T);
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b)
-                rows[m.face_edges[3 * f + a]].push_back({m.face_edges[3 * f + b], cplx(0.0, k * T[3 * a + b])});
+                if (keep(m.face_edges[3 * f + a]) && keep(m.face_edges[3 * f + b]))
+                    rows[m.face_edges[3 * f + a]].push_back({m.face_edges[3 * f + b], cplx(0.0, k * T[3 * a + b])});
     }
     rowptr.assign(m.ne + 1, 0);
     col.clear();
@@ -336,7 +341,15 @@ int setup_device(d3m_problem *h) {
     int rc;
     if ((rc = upload_schedules(h, false)) != D3M_OK) return rc;
 #define UP(dst, vec) if ((rc = h->upload(dst, vec.data(), vec.size() * sizeof(vec[0]))) != D3M_OK) return rc
-    UP(h->d_eprob, h->eprob);
+    {
+        // the device copy marks PEC edges with -1: the residual and norm
+        // kernels leave those rows out
+        std::vector<int32_t> ep = h->eprob;
+        if (!h->mesh.pec.empty())
+            for (int64_t e = 0; e < h->mesh.ne; ++e)
+                if (h->mesh.pec[e]) ep[e] = -1;
+        UP(h->d_eprob, ep);
+    }
     if ((rc = h->zeros(h->d_status, sizeof(int) * (pl.n_status + 1))) != D3M_OK) return rc;
     size_t dr = (size_t)std::max<i64>(pl.d_rows, 1);
     if ((rc = h->zeros(h->D.d, dr * sizeof(double2))) != D3M_OK) return rc;
@@ -1039,6 +1052,10 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
 void make_plan(Plan &pl, const d3m_problem *h, int scope, int s1_block, int k_block, bool k_fuse) {
     build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse);
     if (h->opt.k_multifrontal) build_multifrontal(pl, k_block > 0 ? k_block : 2);
+    // loads on PEC edges are ignored: their subdomain rows start from zero
+    if (h->mesh.n_pec > 0)
+        for (auto &e : pl.split_map)
+            if (e >= 0 && h->mesh.pec[e]) e = -1;
 }
 
 // Re-plans the handle for another pivot scope of step 5 (0: pieces of at most
@@ -1084,8 +1101,8 @@ int replan_scope(d3m_problem *h, int scope) {
 // Host setup of a handle (mesh, decomposition, ordering, plan), then the
 // device upload.  sub_group: problem of every subdomain (empty: one problem).
 int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz, int64_t nt, const int64_t *tets,
-                 const int32_t *part, const double *eps_r, double k, d3m_c128 alpha, const d3m_options *opt,
-                 std::vector<int> sub_group) {
+                 int64_t npec, const int64_t *pec, const int32_t *part, const double *eps_r, double k,
+                 d3m_c128 alpha, const d3m_options *opt, std::vector<int> sub_group) {
     if (opt) h->opt = *opt; else d3m_default_options(&h->opt);
     if (h->opt.quad_points <= 0) h->opt.quad_points = 12;
     if (h->opt.ir_max_iter <= 0 && !opt) h->opt.ir_max_iter = 10;
@@ -1095,6 +1112,7 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
         return fail(D3M_EINVAL, "k_multifrontal must be 0 or 1");
     try {
         build_mesh(h->mesh, nv, xyz, nt, tets);
+        mark_pec(h->mesh, npec, pec);
         h->k = k;
         h->alpha = cplx(alpha.re, alpha.im);
         h->eps.assign(eps_r, eps_r + nt);
@@ -1145,7 +1163,29 @@ void planewave_loads(d3m_problem *h, const double *dirs, const double *pols, int
                 x.im += out[a].imag();
             }
         }
+        if (h->mesh.n_pec > 0)
+            for (int64_t e = 0; e < ne; ++e)
+                if (h->mesh.pec[e]) f[(size_t)c * ne + e] = d3m_c128{0.0, 0.0};
     }
+}
+
+// the tetrahedron holding point r (largest smallest barycentric coordinate,
+// the first one that holds it) and its barycentric coordinates; -1 outside
+i64 locate_point(const Mesh &m, const double *r, double bl[4]) {
+    i64 best = -1;
+    double bestmin = -1e300;
+    for (i64 t = 0; t < m.nt; ++t) {
+        const double *x0 = &m.xyz[3 * m.tets[4 * t]];
+        const double *g = &m.grads[12 * t];
+        double l[4];
+        const double d[3] = {r[0] - x0[0], r[1] - x0[1], r[2] - x0[2]};
+        for (int a = 1; a < 4; ++a) l[a] = g[3 * a] * d[0] + g[3 * a + 1] * d[1] + g[3 * a + 2] * d[2];
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        const double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
+        if (mn > bestmin) { bestmin = mn; best = t; std::memcpy(bl, l, sizeof(l)); }
+        if (mn >= 0) break;
+    }
+    return (best < 0 || bestmin < -1e-12) ? -1 : best;
 }
 }  // namespace
 
@@ -1231,8 +1271,11 @@ int d3m_setup(const d3m_mesh *mesh, const int32_t *part, const double *eps_r, do
     if (!out) return fail(D3M_EINVAL, "null output handle");
     *out = nullptr;
     if (!mesh || !mesh->xyz || !mesh->tets || !part || !eps_r) return fail(D3M_EINVAL, "null argument");
+    if (mesh->n_pec_faces < 0 || (mesh->n_pec_faces > 0 && !mesh->pec_faces))
+        return fail(D3M_EINVAL, "n_pec_faces > 0 needs pec_faces");
     std::unique_ptr<d3m_problem> h(new d3m_problem());
-    int rc = setup_common(h, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, part, eps_r, k, alpha, opt, {});
+    int rc = setup_common(h, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tets, mesh->n_pec_faces,
+                          mesh->pec_faces, part, eps_r, k, alpha, opt, {});
     if (rc != D3M_OK) return rc;
     *out = h.release();
     return D3M_OK;
@@ -1258,6 +1301,7 @@ int d3m_setup_batch(const d3m_batch_item *items, int32_t count, double k, d3m_c1
     std::vector<int64_t> tets;
     std::vector<int32_t> part;
     std::vector<double> eps;
+    std::vector<int64_t> pec;
     std::vector<int> sub_group;
     std::vector<int64_t> vert_off{0};
     try {
@@ -1280,6 +1324,13 @@ int d3m_setup_batch(const d3m_batch_item *items, int32_t count, double k, d3m_c1
                 part.push_back(it.part[t] + sub0);
             }
             eps.insert(eps.end(), it.eps_r, it.eps_r + it.mesh.n_tets);
+            if (it.mesh.n_pec_faces < 0 || (it.mesh.n_pec_faces > 0 && !it.mesh.pec_faces))
+                return fail(D3M_EINVAL, "n_pec_faces > 0 needs pec_faces");
+            for (int64_t x = 0; x < 3 * it.mesh.n_pec_faces; ++x) {
+                const int64_t v = it.mesh.pec_faces[x];
+                if (v < 0 || v >= it.mesh.n_vertices) return fail(D3M_EINVAL, "PEC vertex id out of range");
+                pec.push_back(v + v0);
+            }
             for (int32_t d = 0; d < np; ++d) sub_group.push_back(p);
             sub0 += np;
             vert_off.push_back(v0 + it.mesh.n_vertices);
@@ -1306,7 +1357,8 @@ int d3m_setup_batch(const d3m_batch_item *items, int32_t count, double k, d3m_c1
         }
         for (int q = p + 1; q <= count; ++q) h->prob_edge_off[q] = probe.ne;
     }
-    int rc = setup_common(h, nv, xyz.data(), nt, tets.data(), part.data(), eps.data(), k, alpha, opt, sub_group);
+    int rc = setup_common(h, nv, xyz.data(), nt, tets.data(), (int64_t)pec.size() / 3, pec.data(), part.data(),
+                          eps.data(), k, alpha, opt, sub_group);
     if (rc != D3M_OK) return rc;
     *out = h.release();
     return D3M_OK;
@@ -1467,27 +1519,45 @@ int d3m_rhs_planewave_batch(d3m_handle h, const double *dirs, const double *pols
     return D3M_OK;
 }
 
+int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int32_t nrhs, d3m_c128 *f) {
+    if (!h || !pos || !moment || !f) return fail(D3M_EINVAL, "null argument");
+    if (nrhs < 1) return fail(D3M_EINVAL, "nrhs must be >= 1");
+    if (h->n_problems != 1) return fail(D3M_EINVAL, "dipole loads need a single-problem handle");
+    const Mesh &m = h->mesh;
+    static const int te[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    const int64_t ne = m.ne;
+    std::memset(f, 0, sizeof(d3m_c128) * (size_t)nrhs * ne);
+    const cplx scale = cplx(0.0, -h->k * D3M_ETA0);
+    for (int c = 0; c < nrhs; ++c) {
+        double bl[4];
+        const i64 t = locate_point(m, pos + 3 * c, bl);
+        if (t < 0) return fail(D3M_EINVAL, "dipole " + std::to_string(c) + " outside the mesh");
+        const double *g = &m.grads[12 * t];
+        const d3m_c128 *mo = moment + 3 * c;
+        for (int a = 0; a < 6; ++a) {
+            const int i = te[a][0], j = te[a][1];
+            const i64 e = m.tet_edges[6 * t + a];
+            if (!m.pec.empty() && m.pec[e]) continue;
+            cplx dot = 0.0;
+            for (int x = 0; x < 3; ++x)
+                dot += cplx(mo[x].re, mo[x].im) * (bl[i] * g[3 * j + x] - bl[j] * g[3 * i + x]);
+            const cplx v = scale * dot;
+            f[(size_t)c * ne + e].re += v.real();
+            f[(size_t)c * ne + e].im += v.imag();
+        }
+    }
+    return D3M_OK;
+}
+
 int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges, double *coef) {
     if (!h || !pts || !edges || !coef) return fail(D3M_EINVAL, "null argument");
     if (h->n_problems != 1) return fail(D3M_EINVAL, "probe needs a single-problem handle");
     const Mesh &m = h->mesh;
     static const int te[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
     for (int p = 0; p < n; ++p) {
-        const double *r = pts + 3 * p;
-        i64 best = -1;
-        double bestmin = -1e300, bl[4] = {0, 0, 0, 0};
-        for (i64 t = 0; t < m.nt; ++t) {
-            const double *x0 = &m.xyz[3 * m.tets[4 * t]];
-            const double *g = &m.grads[12 * t];
-            double l[4];
-            double d[3] = {r[0] - x0[0], r[1] - x0[1], r[2] - x0[2]};
-            for (int a = 1; a < 4; ++a) l[a] = g[3 * a] * d[0] + g[3 * a + 1] * d[1] + g[3 * a + 2] * d[2];
-            l[0] = 1.0 - l[1] - l[2] - l[3];
-            double mn = std::min(std::min(l[0], l[1]), std::min(l[2], l[3]));
-            if (mn > bestmin) { bestmin = mn; best = t; std::memcpy(bl, l, sizeof(l)); }
-            if (mn >= 0) break;
-        }
-        if (best < 0 || bestmin < -1e-12) return fail(D3M_EINVAL, "probe point outside the mesh");
+        double bl[4] = {0, 0, 0, 0};
+        const i64 best = locate_point(m, pts + 3 * p, bl);
+        if (best < 0) return fail(D3M_EINVAL, "probe point outside the mesh");
         const double *g = &m.grads[12 * best];
         for (int a = 0; a < 6; ++a) {
             int i = te[a][0], j = te[a][1];

@@ -7,7 +7,10 @@
 // +alpha T and A_q gets -alpha T ("loss or gain at the interfaces") while
 // D_p = +1 and D_q = -1 on the shared edge; edges shared by m > 2 subdomains
 // carry m - 1 multipliers along a spanning tree of the subdomain pairs that
-// share a triangle containing the edge (Kruskal, lexicographic).
+// share a triangle containing the edge (Kruskal, lexicographic).  Edges of
+// PEC triangles (tangential field zero) carry no multiplier, and their rows
+// of A_d are the identity (every other entry of the row and column dropped),
+// so the subdomain solves leave them at the zero load they are given.
 #include <algorithm>
 #include <array>
 #include <functional>
@@ -127,7 +130,7 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
             i64 mult = dc.sub_ptr[e + 1] - dc.sub_ptr[e];
             size_t c0 = c;
             while (c < cand.size() && cand[c][0] == e) ++c;
-            if (mult < 2) continue;
+            if (mult < 2 || (!m.pec.empty() && m.pec[e])) continue;
             Dsu dsu;
             i64 chosen = 0;
             for (size_t i = c0; i < c; ++i)  // candidates sorted by (p, q)
@@ -178,24 +181,36 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
     // collect keyed contributions: (row, col) -> value parts
     std::vector<std::vector<std::array<i64, 4>>> tetc(N);   // (row, col, tet, a*6+b)
     std::vector<std::vector<std::pair<std::array<i64, 2>, cplx>>> statc(N);
+    auto is_pec = [&](i64 e) { return !m.pec.empty() && m.pec[e] != 0; };
     for (i64 t = 0; t < m.nt; ++t) {
         Subdomain &S = dc.sub[part[t]];
         i64 r[6];
-        for (int a = 0; a < 6; ++a) r[a] = S.row_of(m.tet_edges[6 * t + a]);
+        bool z[6];
+        for (int a = 0; a < 6; ++a) {
+            r[a] = S.row_of(m.tet_edges[6 * t + a]);
+            z[a] = is_pec(m.tet_edges[6 * t + a]);
+        }
         for (int a = 0; a < 6; ++a)
             for (int b = 0; b < 6; ++b)
-                if (r[a] >= r[b]) tetc[part[t]].push_back({r[a], r[b], t, a * 6 + b});
+                if (r[a] >= r[b] && !z[a] && !z[b]) tetc[part[t]].push_back({r[a], r[b], t, a * 6 + b});
     }
     auto add_face = [&](int d, i64 f, cplx scale) {
         Subdomain &S = dc.sub[d];
         double T[9];
         tri_tangential_mass(m, f, T);
         i64 r[3];
-        for (int a = 0; a < 3; ++a) r[a] = S.row_of(m.face_edges[3 * f + a]);
+        bool z[3];
+        for (int a = 0; a < 3; ++a) {
+            r[a] = S.row_of(m.face_edges[3 * f + a]);
+            z[a] = is_pec(m.face_edges[3 * f + a]);
+        }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b)
-                if (r[a] >= r[b]) statc[d].push_back({{r[a], r[b]}, scale * T[3 * a + b]});
+                if (r[a] >= r[b] && !z[a] && !z[b]) statc[d].push_back({{r[a], r[b]}, scale * T[3 * a + b]});
     };
+    for (int d = 0; d < N; ++d)
+        for (i64 r = 0; r < dc.sub[d].n; ++r)
+            if (is_pec(dc.sub[d].edges[r])) statc[d].push_back({{r, r}, cplx(1.0, 0.0)});
     const cplx jk(0.0, k);
     for (i64 f : dc.bface) add_face(part[m.face_tet[2 * f]], f, jk);
     for (size_t i = 0; i < dc.iface.size(); ++i) {

@@ -280,4 +280,24 @@ void face_planewave_load(const Mesh &m, i64 f, double k, const double d[3],
     }
 }
 
+void mark_pec(Mesh &m, i64 nfaces, const i64 *faces) {
+    m.pec.assign(m.ne, 0);
+    m.n_pec = 0;
+    for (i64 f = 0; f < nfaces; ++f) {
+        std::array<i64, 3> v{faces[3 * f], faces[3 * f + 1], faces[3 * f + 2]};
+        std::sort(v.begin(), v.end());
+        // faces are stored in increasing (v0, v1, v2) order
+        i64 lo = 0, hi = m.nf;
+        while (lo < hi) {
+            const i64 mid = (lo + hi) / 2;
+            const std::array<i64, 3> w{m.faces[3 * mid], m.faces[3 * mid + 1], m.faces[3 * mid + 2]};
+            if (w < v) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= m.nf || m.faces[3 * lo] != v[0] || m.faces[3 * lo + 1] != v[1] || m.faces[3 * lo + 2] != v[2])
+            throw Error{-1, "PEC triangle " + std::to_string(f) + " is not a face of the mesh"};
+        for (int a = 0; a < 3; ++a) m.pec[m.face_edges[3 * lo + a]] = 1;
+    }
+    for (i64 e = 0; e < m.ne; ++e) m.n_pec += m.pec[e];
+}
+
 }  // namespace d3m

@@ -36,11 +36,16 @@ struct Mesh {
     std::vector<i64> face_edges;    // [nf][3] edges (01, 02, 12)
     std::vector<double> volume;     // [nt]
     std::vector<double> grads;      // [nt][4][3] barycentric gradients
+    std::vector<char> pec;          // [ne] 1: edge of a PEC triangle (tangential field zero, no unknown)
+    i64 n_pec = 0;
 };
 
 // Builds topology and per-tetrahedron geometry; throws Error on a degenerate
 // tetrahedron or a non-manifold face.
 void build_mesh(Mesh &m, i64 nv, const double *xyz, i64 nt, const i64 *tets);
+// Marks the edges of the given triangles (vertex-id triples, any order) as
+// PEC; throws Error when a triple is not a face of the mesh.
+void mark_pec(Mesh &m, i64 nfaces, const i64 *faces);
 
 // Element matrices (Whitney 1-forms).  Kc and M are 6x6 row-major; T is 3x3.
 void tet_curl_mass(const Mesh &m, i64 t, double Kc[36], double M[36]);

@@ -602,7 +602,8 @@ __global__ __launch_bounds__(256) void vtranspose_kernel(double2 *Et, const doub
 // on right-hand side l % 16 of row l / 16 of the wave's four current rows, so
 // the gather of Et for one matrix entry is a contiguous 256-byte run shared
 // by 16 lanes.  nmax[p * nrhs + c] (zeroed by the caller) gets the largest
-// |r[c][e]| (modulus) over the rows e of problem p = eprob[e].
+// |r[c][e]| (modulus) over the rows e of problem p = eprob[e]; rows with
+// eprob[e] < 0 (PEC edges) get r = 0 and no norm contribution.
 constexpr int RES_ROWS = 256;
 
 __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2 *f, const double2 *Et,
@@ -623,6 +624,10 @@ __global__ __launch_bounds__(256) void residual_kernel(double2 *r, const double2
         const int64_t row = base + 16 * it + 4 * wave + rs;
         if (row >= ne) break;
         const int p = eprob[row];
+        if (p < 0) {  // a PEC edge: no unknown, no residual
+            if (cok) r[(int64_t)c * ne + row] = make_double2(0, 0);
+            continue;
+        }
         if (p != pcur) {  // a new problem (batches): fold this thread's maximum so far
             if (pcur >= 0 && cok) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c], m);
             pcur = p;
@@ -681,6 +686,7 @@ __global__ __launch_bounds__(256) void rownorm_max_kernel(unsigned long long *nm
         const int64_t e = base + threadIdx.x + 256 * i;
         if (e >= ne) break;
         const int p = eprob[e];
+        if (p < 0) continue;  // a PEC edge: not part of the norm
         if (p != pcur) {
             if (pcur >= 0) atomic_max_bits(&nmax[(int64_t)pcur * nrhs + c], m[0]);
             pcur = p;

@@ -1,11 +1,12 @@
 """Writes the oracle's solutions of the full-size workloads at sampled
-unknowns: tests/golden/fullsize_config{2,4,5}.npz and fullsize_config3.npz.
+unknowns: tests/golden/fullsize_config{2,4,5}.npz, fullsize_config3.npz and
+fullsize_pec.npz (the PEC-plate workload: plane waves and point dipoles).
 
 Imports only ``oracle`` and ``workloads``: every stored value is the CPU
 oracle's (the seven steps of Section II in complex128, sparse LU per
 subdomain, Algorithm 1 on K).  Run from the repository root:
 
-    python tests/golden/make_fullsize_fixtures.py 2 4 5 3
+    python tests/golden/make_fullsize_fixtures.py 2 4 5 3 pec
 
 Each file holds, for one workload (one problem of the batch for config 3,
 keys prefixed ``p<index>_``):
@@ -17,7 +18,8 @@ keys prefixed ``p<index>_``):
   lam        complex128 [nrhs, nl] oracle lambda there
   lam_inf    float64 [nrhs]      max over all multipliers of |lambda|
   residual   float64 [nrhs]      ||S E - f||_inf / ||f||_inf of the oracle
-                                 solution (oracle S and f)
+                                 solution (oracle S and f; on the unknowns,
+                                 i.e. without PEC edges)
   f          complex128 [nrhs, ns] oracle plane-wave load at the sampled edges
 and the oracle's phase timings on the machine that wrote it (seconds).  For
 the dielectric-sphere workload (receivers and learnable tetrahedra) also
@@ -29,7 +31,9 @@ the dielectric-sphere workload (receivers and learnable tetrahedra) also
   grad_max   float64             max |dL/d eps_r| over the learnable tetrahedra
 
 The right-hand sides are the oracle's plane-wave loads for the workload's
-directions and polarisations (Section II, second line of the BVP).
+directions and polarisations (Section II, second line of the BVP), followed
+for the PEC workload by its point-dipole loads (the impressed current of the
+first line).
 """
 from __future__ import annotations
 
@@ -44,17 +48,17 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
-from oracle.d3m import D3MOracle, relative_residual  # noqa: E402
+from oracle.d3m import D3MOracle  # noqa: E402
 from oracle.fem import probe_matrix  # noqa: E402
 
-SAMPLES = {2: (4096, 2048), 4: (2048, 1024), 5: (4096, 2048), 3: (256, 128)}
+SAMPLES = {2: (4096, 2048), 4: (2048, 1024), 5: (4096, 2048), 3: (256, 128), "pec": (4096, 2048)}
 
 
 def _sample(rng, o, n_edge, n_lm):
     dec = o.dec
-    mult = np.array([len(s) for s in dec.sub_of_edge])
+    mult = np.array([len(s) for s in dec.sub_of_edge])  # 0 on PEC edges
     shared = np.nonzero(mult >= 2)[0]
-    single = np.nonzero(mult < 2)[0]
+    single = np.nonzero(mult == 1)[0]
     h = min(n_edge // 2, shared.size)
     e = np.concatenate([rng.choice(shared, h, replace=False),
                         rng.choice(single, min(n_edge - h, single.size), replace=False)])
@@ -71,11 +75,14 @@ def solve_problem(prob, seed, n_edge, n_lm, log):
     t2 = time.perf_counter()
     log(f"  factor {t2 - t1:.1f} s {o.timings}")
     f = o.fem.planewave_rhs(prob.dirs, prob.pols)
+    if prob.dip_pos.shape[0]:
+        f = np.concatenate([f, o.fem.dipole_rhs(prob.dip_pos, prob.dip_moment)])
     E = o.solve(f)
     t3 = time.perf_counter()
     log(f"  solve {t3 - t2:.1f} s")
-    r = np.abs((o.fem.S @ E.T).T - f).max(axis=1) / np.abs(f).max(axis=1)
-    assert float(r.max()) == relative_residual(o.fem.S, E, f)
+    free = o.fem.free
+    r = np.abs((o.fem.system() @ E[:, free].T).T - f[:, free]).max(axis=1) / np.abs(f[:, free]).max(axis=1)
+    assert float(r.max()) == o.fem.relative_residual(E, f)
     log(f"  residual {r.max():.2e}")
     rng = np.random.default_rng(seed)
     e, lm = _sample(rng, o, n_edge, n_lm)
@@ -106,9 +113,11 @@ def main(cfgs):
 
     for cfg in cfgs:
         n_edge, n_lm = SAMPLES[cfg]
-        path = os.path.join(HERE, f"fullsize_config{cfg}.npz")
+        path = os.path.join(HERE, "fullsize_pec.npz" if cfg == "pec" else f"fullsize_config{cfg}.npz")
         log(f"config {cfg} -> {path}")
-        if cfg == 3:
+        if cfg == "pec":
+            data = solve_problem(W.make_pec_config(), 1006, n_edge, n_lm, log)
+        elif cfg == 3:
             probs = W.make_batch_config()
             data = {}
             for p, prob in enumerate(probs):
@@ -123,4 +132,4 @@ def main(cfgs):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [2, 4, 5, 3])
+    main([a if a == "pec" else int(a) for a in sys.argv[1:]] or [2, 4, 5, 3, "pec"])

@@ -68,7 +68,8 @@ def load_fixture(cfg, prefix=""):
     import os
 
     import pytest
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fullsize_config{cfg}.npz")
+    name = "fullsize_pec.npz" if cfg == "pec" else f"fullsize_config{cfg}.npz"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     if not os.path.exists(path):
         pytest.skip(f"oracle fixture {os.path.basename(path)} not written yet "
                     "(tests/golden/make_fullsize_fixtures.py)")
