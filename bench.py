@@ -33,7 +33,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", default="4", choices=["1", "2", "3", "4", "5", "pec"],
+                    help="workload: configurations 1-5, or pec (24^3 hexes with two PEC plates, plane waves "
+                         "and point dipoles)")
     ap.add_argument("--batch-count", type=int, default=32, help="problems of the configuration 3 batch")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--multifrontal", action="store_true",
@@ -249,7 +251,7 @@ def error_vs_oracle(E, cfg):
     """Largest over right-hand sides of max |E - E_oracle| / max |E_oracle|
     at the sampled edges of the committed oracle fixture (None without one)."""
     import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", f"fullsize_config{cfg}.npz")
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_pec.npz" if cfg == "pec" else f"fullsize_config{cfg}.npz")
     if not os.path.exists(path):
         return None
     with np.load(path, allow_pickle=False) as z:
@@ -346,6 +348,7 @@ def _roofline(up, info, steps, prec, traffic):
 
 def main():
     args = parse()
+    args.config = args.config if args.config == "pec" else int(args.config)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "layout of this path is a design note, not a runnable configuration", file=sys.stderr)
@@ -362,7 +365,7 @@ def main():
     import workloads as W
     from paper_2002_05018_amd import FP32_IR, FP64, Solver
 
-    prob = W.make_config(args.config)
+    prob = W.make_pec_config() if args.config == "pec" else W.make_config(args.config)
     t0 = time.perf_counter()
     # timed steps time only the update GEMM launches (HIP events on their
     # streams); a separate untimed pass with every kernel group timed gives
@@ -371,6 +374,9 @@ def main():
     setup_s = time.perf_counter() - t0
     info = solver.info
     f_host = solver.rhs_planewave(prob.dirs, prob.pols)
+    if prob.dip_pos.shape[0]:  # point dipoles after the plane waves
+        f_host = np.concatenate([f_host, solver.rhs_dipole(prob.dip_pos, prob.dip_moment)])
+    nrhs = f_host.shape[0]
     f = torch.from_numpy(f_host).cuda()
     E = torch.empty_like(f)
     torch.cuda.synchronize()
@@ -397,8 +403,10 @@ def main():
     E64 = E.clone()  # FP64 solution: reference for the FP32 form's difference
     E64_host = E64.cpu().numpy()
     solve_ms = sol["total_ms"] / nphase
-    solve_alg = info["solve_bytes"] + info["solve_vector_bytes"] * prob.nrhs
-    cfg_name = {2: "24^3 hexes (102,024 edges), 4x4x4 box subdomains, 8 plane-wave RHS",
+    solve_alg = info["solve_bytes"] + info["solve_vector_bytes"] * nrhs
+    cfg_name = {"pec": "24^3 hexes (102,024 edges), 4x4x4 box subdomains, two PEC plates, 4 plane-wave and "
+                       "4 point-dipole RHS",
+                2: "24^3 hexes (102,024 edges), 4x4x4 box subdomains, 8 plane-wave RHS",
                 4: "48^3 hexes (795,024 edges), 8x8x8 box subdomains, 32 plane-wave RHS",
                 5: "32^3 hexes (238,688 edges), 4x4x4 box subdomains, dielectric sphere, 4 plane-wave RHS",
                 1: "6^3 hexes (1,854 edges), 2x2x1 box subdomains, 1 plane-wave RHS"}[args.config]
@@ -419,7 +427,7 @@ def main():
                                f"k={prob.k:.4f}; FP64 factor+solve, FP32 factor + FP64 refinement "
                                f"to 1e-10 side by side",
                    "n_edges": info["n_edges"], "n_lm": info["n_lm"], "n_blocks": info["n_blocks"],
-                   "n_subdomains": info["n_subdomains"], "nrhs": prob.nrhs, "precision": "fp64",
+                   "n_subdomains": info["n_subdomains"], "nrhs": nrhs, "precision": "fp64",
                    "step5": "multifrontal" if args.multifrontal else "right-looking"},
         "roofline": _roofline(up, info, args.steps, "c128",
                               None if args.multifrontal else measured_traffic(args.config, "fp64")),
