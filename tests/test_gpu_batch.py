@@ -210,3 +210,36 @@ def test_overlapped_k_schedule_is_bitwise_identical():
         got = g.solve(f).cpu().numpy()
         torch.cuda.synchronize()
         assert np.array_equal(got, want)
+
+
+def test_batch_multifrontal_and_pec_problem():
+    """The batching form with step 5 in multifrontal form, and a batch whose
+    middle problem holds a PEC plate: every problem equals the oracle run on
+    it alone (its PEC plate included) to 1e-10, E is zero on the PEC edges."""
+    from oracle.d3m import D3MOracle
+    from paper_2002_05018_amd import Solver
+    probs, s, f, eo, ref = _batch()
+    mf = Solver.batch(probs, probs[0].k, probs[0].alpha, multifrontal=True)
+    assert mf.query()["k_multifrontal"] == 1
+    mf.factor("fp64")
+    E = mf.solve(torch.from_numpy(f).cuda()).cpu().numpy()
+    for p in range(len(probs)):
+        assert_rhs_close(E[:, eo[p]:eo[p + 1]], ref[p], 1e-10, f"multifrontal problem {p}")
+    import copy
+    pp = [copy.copy(q) for q in probs]
+    n = pp[1].n
+    pp[1].pec_faces = W.plate_faces(n, pp[1].tets, 2, n // 2, [1, 1], [n - 1, n - 2])
+    b = Solver.batch(pp, pp[0].k, pp[0].alpha)
+    fb = b.rhs_planewave_batch(np.stack([q.dirs for q in pp]), np.stack([q.pols for q in pp]))
+    _, eb, _ = b.layout()
+    b.factor("fp64")
+    Eb, info = b.solve(torch.from_numpy(fb).cuda(), with_info=True)
+    Eb = Eb.cpu().numpy()
+    assert info["residual"] <= 1e-10
+    for p, prob in enumerate(pp):
+        o = D3MOracle.from_problem(prob).factor()
+        Eo = o.solve(fb[:, eb[p]:eb[p + 1]])
+        Ep = Eb[:, eb[p]:eb[p + 1]]
+        assert not np.any(Ep[:, o.fem.pec])
+        assert_rhs_close(Ep, Eo, 1e-10, f"PEC batch problem {p}")
+    assert o.fem.pec.sum() == 0 and D3MOracle.from_problem(pp[1]).fem.pec.sum() > 0
