@@ -277,7 +277,10 @@ int d3m_factor_growth(d3m_handle h, double *lhat_subdomains, double *lhat_k);
  *   rhs  [nrhs][n_edges] complex128 (global load f, row per right-hand side).
  *   E    [nrhs][n_edges] complex128 output.
  *   info optional diagnostics (NULL allowed).
- * FP32_IR handles refine in FP64 on the global system until ir_tol.
+ * FP32_IR handles refine in FP64 on the global system until ir_tol: each
+ * step computes r = f - S E in FP64 and adds the FP32 solution of S d = r,
+ * over the right-hand sides whose relative residual is still above ir_tol
+ * (in some problem of a batch); the others keep their field.
  * Errors: D3M_ESTATE (not factored), D3M_EINVAL (nrhs < 1), D3M_ENOCONV
  * (refinement missed ir_tol; E holds the best iterate), D3M_EHIP. */
 int d3m_solve(d3m_handle h, const d3m_c128 *rhs, int32_t nrhs, d3m_c128 *E,

@@ -102,6 +102,7 @@ struct d3m_problem {
     DevBuf vec[2][VARR_COUNT];
     int vec_nrhs[2] = {0, 0};
     DevBuf stage_f, stage_E, stage_r, stage_w, stage_g;
+    DevBuf stage_rc, stage_ec;  // refinement: residual and field rows of the right-hand sides still refined
     DevBuf stage_et;  // the field transposed (right-hand sides of an edge contiguous) for the residual
     DevBuf norms;
     double2 *d_unused = nullptr;
@@ -161,7 +162,7 @@ struct d3m_problem {
             for (auto &b : arr[pr]) if (b.p) (void)hipFree(b.p);
             for (auto &b : vec[pr]) if (b.p) (void)hipFree(b.p);
         }
-        for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &stage_et, &norms})
+        for (DevBuf *b : {&stage_f, &stage_E, &stage_r, &stage_w, &stage_g, &stage_rc, &stage_ec, &stage_et, &norms})
             if (b->p) (void)hipFree(b->p);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         for (auto e : sync_pool) (void)hipEventDestroy(e);
@@ -959,14 +960,44 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     int it = 0;
     double res = 0.0;
     bool ok = false;
+    const int64_t ne = h->mesh.ne;
+    const size_t row = sizeof(double2) * (size_t)ne;
     for (;;) {
         if ((rc = residual_inf(h, f, E, nrhs, rn, s))) return rc;
         res = relative_residual(rn, fn);
         if (res <= h->opt.ir_tol) { ok = true; break; }
         if (it >= h->opt.ir_max_iter) break;
-        if ((rc = solve_pass<float>(h, (double2 *)h->stage_r.p, E, nrhs, true, s))) return rc;
+        // right-hand sides still above the tolerance in some problem (a NaN
+        // residual counts as not converged); the others keep their field
+        std::vector<int> todo;
+        for (int c = 0; c < nrhs; ++c) {
+            bool done = true;
+            for (int p = 0; p < h->n_problems; ++p) {
+                const size_t i = (size_t)p * nrhs + c;
+                const double q = fn[i] > 0 ? rn[i] / fn[i] : rn[i];
+                if (!(q <= h->opt.ir_tol)) done = false;
+            }
+            if (!done) todo.push_back(c);
+        }
+        const int m = (int)todo.size();
+        if (m == nrhs) {
+            if ((rc = solve_pass<float>(h, (double2 *)h->stage_r.p, E, nrhs, true, s))) return rc;
+        } else {
+            // one correction solve over those right-hand sides only: their
+            // residual and field rows gathered, corrected, written back
+            if ((rc = h->ensure(h->stage_rc, row * m)) || (rc = h->ensure(h->stage_ec, row * m))) return rc;
+            double2 *rcm = (double2 *)h->stage_rc.p, *ecm = (double2 *)h->stage_ec.p;
+            for (int i = 0; i < m; ++i) {
+                HIPCHK(hipMemcpyAsync(rcm + (size_t)i * ne, (double2 *)h->stage_r.p + (size_t)todo[i] * ne, row,
+                                      hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(ecm + (size_t)i * ne, E + (size_t)todo[i] * ne, row, hipMemcpyDeviceToDevice, s));
+            }
+            if ((rc = solve_pass<float>(h, rcm, ecm, m, true, s))) return rc;
+            for (int i = 0; i < m; ++i)
+                HIPCHK(hipMemcpyAsync(E + (size_t)todo[i] * ne, ecm + (size_t)i * ne, row, hipMemcpyDeviceToDevice, s));
+        }
         if (info) {
-            if ((rc = copy_discrepancy<float>(h, nrhs, d1, s))) return rc;
+            if ((rc = copy_discrepancy<float>(h, m, d1, s))) return rc;
             disc += d1;
         }
         ++it;

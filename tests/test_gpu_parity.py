@@ -272,3 +272,21 @@ def test_growth_monitor_and_whole_block_fallback():
     assert_rhs_close(sf.solve(torch.from_numpy(f).cuda()).cpu().numpy(), Eo, 1e-10, "E")
     sz, perm, d0, d1, L = sf.export("kfactor")
     assert list(sz) == [int(o.dec.block_start[b + 1] - o.dec.block_start[b]) for b in sf.export("order")]
+
+
+def test_fp32_refinement_refines_only_unconverged_rhs():
+    """A zero right-hand side is solved exactly by the first FP32 pass, so
+    every later correction runs over the other right-hand sides only
+    (gathered, corrected, written back): the field of the loaded ones equals
+    the refinement run on them alone, the zero one stays exactly zero."""
+    from paper_2002_05018_amd import Solver
+    prob, s, o, f, Eo, lamo = _pair("cross_lines_2x2x2")
+    s.factor("fp32_ir")
+    f2 = np.concatenate([f[:1], np.zeros_like(f[:1]), f[1:]])
+    E2, info2 = s.solve(torch.from_numpy(f2).cuda(), with_info=True)
+    E1, info1 = s.solve(torch.from_numpy(f).cuda(), with_info=True)
+    E2, E1 = E2.cpu().numpy(), E1.cpu().numpy()
+    assert info2["converged"] and info2["residual"] <= 1e-10 and info2["iterations"] >= 1, info2
+    assert not np.any(E2[1])
+    assert_rhs_close(np.concatenate([E2[:1], E2[2:]]), E1, 1e-12, "refined subset vs all")
+    assert_rhs_close(np.concatenate([E2[:1], E2[2:]]), Eo, 1e-9, "refined subset vs oracle")
