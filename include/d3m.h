@@ -336,6 +336,21 @@ int d3m_rhs_planewave_batch(d3m_handle h, const double *dirs,
  * handles only; D3M_EINVAL for a point outside the mesh. */
 int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int32_t nrhs, d3m_c128 *f);
 
+/* Static race check of the factorisation schedule of the handle's plan and
+ * tuning (no GPU needed: host_only handles work): the launches of one
+ * factorisation are replayed with their streams, event records and waits,
+ * and every tile each work-group reads or writes (working, panel, factor
+ * and TT tiles, pivot-data rows) is checked against the other accesses that
+ * are not ordered before or after it.  Returns the number of conflicting
+ * pairs found (0: race-free) or a negative error; a description of the
+ * first ones is copied to report (NUL-terminated, at most report_bytes,
+ * NULL allowed).  flags: bit 0 models the side-stream schedule for
+ * whole-block pivot units too (which the library does not launch); bit 1
+ * leaves out every stream wait for earlier side-stream updates (a planted
+ * mistake, so tests can see the check report it).  For the race detection
+ * of the factor schedules (tests), not the paper. */
+int64_t d3m_debug_check_schedule(d3m_handle h, int32_t flags, char *report, int64_t report_bytes);
+
 /* Whitney field evaluation at points: for point m, E(r_m) = sum_a c[m][a][:] *
  * u[edge[m][a]] over the six edges of the tetrahedron containing r_m.
  *   pts [n][3]; edges [n][6] (int64) and coef [n][6][3] (double) host outputs.

@@ -42,7 +42,7 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
                     "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth",
-                    "d3m_solve_noalloc", "d3m_rhs_dipole"]
+                    "d3m_solve_noalloc", "d3m_rhs_dipole", "d3m_debug_check_schedule"]
 
 
 class d3m_c128(C.Structure):
@@ -131,6 +131,8 @@ _lib.d3m_adjoint.argtypes = [_h, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, 
 _lib.d3m_rhs_planewave.argtypes = [_h, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_void_p]
 _lib.d3m_probe.argtypes = [_h, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
 _lib.d3m_rhs_dipole.argtypes = [_h, C.POINTER(C.c_double), C.c_void_p, C.c_int32, C.c_void_p]
+_lib.d3m_debug_check_schedule.argtypes = [_h, C.c_int32, C.c_char_p, C.c_int64]
+_lib.d3m_debug_check_schedule.restype = C.c_int64
 _lib.d3m_query.argtypes = [_h, C.POINTER(d3m_info)]
 _lib.d3m_destroy.argtypes = [_h]
 _lib.d3m_destroy.restype = None
@@ -378,6 +380,17 @@ class Solver:
         _check(_lib.d3m_rhs_planewave(self._handle, _ptr(d, C.c_double), _ptr(p, C.c_double), d.shape[0],
                                       C.c_void_p(f.ctypes.data)))
         return f
+
+    def check_schedule(self, force_side=False, drop_waits=False):
+        """Static race check of the factorisation schedule (no GPU): the
+        number of unordered conflicting tile accesses and a description.
+        drop_waits plants a missing-wait mistake into the modelled schedule."""
+        buf = C.create_string_buffer(8192)
+        n = _lib.d3m_debug_check_schedule(self._handle, int(bool(force_side)) | (2 if drop_waits else 0), buf,
+                                          len(buf))
+        if n < 0:
+            _check(int(n))
+        return int(n), buf.value.decode()
 
     def rhs_dipole(self, pos, moment):
         """Point-dipole loads (impressed currents), one per right-hand side:

@@ -16,6 +16,7 @@
 #include "../../include/d3m.h"
 #include "host/plan.hpp"
 #include "host/problem.hpp"
+#include "host/race.hpp"
 #include "kernels/launch.hpp"
 #include "noalloc.hpp"
 
@@ -1578,6 +1579,34 @@ int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int3
         }
     }
     return D3M_OK;
+}
+
+int64_t d3m_debug_check_schedule(d3m_handle h, int32_t flags, char *report, int64_t report_bytes) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (flags < 0 || flags > 3) return fail(D3M_EINVAL, "flags must be in [0, 3]");
+    const bool force_side = (flags & 1) != 0;
+    ScheduleModel m;
+    m.lookahead_tasks = h->tune.lookahead_tasks;
+    m.side_early = h->tune.side_early;
+    m.k_overlap = h->tune.k_overlap;
+    // the streams the factorisation takes: whole-block units run the K phase
+    // on one stream (run_factor_sweep) unless force_side asks for the
+    // side-stream schedule anyway
+    m.one_stream_k = h->opt.pivot_scope == 1 && !force_side;
+    m.drop_waits = (flags & 2) != 0;
+    std::string rep;
+    int64_t races = 0;
+    try {
+        races = check_factor_schedule(h->pl, m, rep);
+    } catch (const std::bad_alloc &) {
+        return fail(D3M_ENOMEM, "host allocation failed in the schedule check");
+    }
+    if (report && report_bytes > 0) {
+        const size_t n = std::min<size_t>(rep.size(), (size_t)report_bytes - 1);
+        std::memcpy(report, rep.data(), n);
+        report[n] = 0;
+    }
+    return races;
 }
 
 int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges, double *coef) {
