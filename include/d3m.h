@@ -347,9 +347,24 @@ int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int3
  * NULL allowed).  flags: bit 0 models the side-stream schedule for
  * whole-block pivot units too (which the library does not launch); bit 1
  * leaves out every stream wait for earlier side-stream updates (a planted
- * mistake, so tests can see the check report it).  For the race detection
- * of the factor schedules (tests), not the paper. */
+ * mistake, so tests can see the check report it).  Bit 2 checks the
+ * work-queue form of the two K solve sweeps instead (d3m_tuning.solve_chain):
+ * a host simulation in which workers take the items from one counter and
+ * wait on the tiles' write counts as the kernel does, under pseudo-random
+ * interleavings; it counts every item that would see a tile with other
+ * writes than the level-by-level order gives it, and a stalled queue
+ * (D3M_EINVAL where the plan has no such form); bit 3 then leaves out each
+ * item's first wait (planted mistake).  For the race detection of the
+ * factor schedules and the queue (tests), not the paper. */
 int64_t d3m_debug_check_schedule(d3m_handle h, int32_t flags, char *report, int64_t report_bytes);
+
+/* Bound of one dependency wait of the work-queue K solve sweeps
+ * (d3m_tuning.solve_chain), in seconds of the device's wall clock (default 2;
+ * 0 makes every wait that is not met at once run out, so a test can see the
+ * solve fail with D3M_EHIP while every kernel still ends normally).
+ * Errors: D3M_EINVAL (seconds outside [0, 60]), D3M_ESTATE (host-only
+ * handle).  For tests of the failure path, not the paper. */
+int d3m_debug_chain_wait_limit(d3m_handle h, double seconds);
 
 /* Whitney field evaluation at points: for point m, E(r_m) = sum_a c[m][a][:] *
  * u[edge[m][a]] over the six edges of the tetrahedron containing r_m.
@@ -414,7 +429,20 @@ typedef struct {
                                 chain segment overlap the next segment's pivot
                                 chain; 0 (default): one side stream, each step
                                 waiting for the previous step's side updates */
-    int32_t reserved[2];
+    int32_t solve_chain;     /* 1: each of the two solve sweeps over the
+                                factor of -K runs as one launch whose
+                                work-groups take the update tasks in the
+                                level-by-level order from a work queue, each
+                                waiting (bounded, 2 s) only for the writes of
+                                the vector tiles it reads; same results bit
+                                for bit.  A wait that runs out fails the
+                                solve with D3M_EHIP (d3m_solve_noalloc: the
+                                next d3m_solve or d3m_adjoint on the handle
+                                reports it).  Ignored where the plan holds
+                                diagonal blocks of several tiles (whole-block
+                                pivot units); 0 (default): one launch per
+                                level and phase                              */
+    int32_t reserved[1];
 } d3m_tuning;
 
 /* Read / replace the tuning.  A new s1_block, k_block or k_fuse rebuilds the factor schedule

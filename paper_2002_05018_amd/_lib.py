@@ -42,7 +42,8 @@ exported_symbols = ["d3m_default_options", "d3m_setup", "d3m_update_eps", "d3m_f
                     "d3m_destroy", "d3m_last_error", "d3m_set_profile", "d3m_kernel_stats",
                     "d3m_debug_export", "d3m_setup_batch", "d3m_batch_layout", "d3m_rhs_planewave_batch",
                     "d3m_get_tuning", "d3m_set_tuning", "d3m_set_graphs", "d3m_debug_bk", "d3m_factor_growth",
-                    "d3m_solve_noalloc", "d3m_rhs_dipole", "d3m_debug_check_schedule"]
+                    "d3m_solve_noalloc", "d3m_rhs_dipole", "d3m_debug_check_schedule",
+                    "d3m_debug_chain_wait_limit"]
 
 
 class d3m_c128(C.Structure):
@@ -97,7 +98,7 @@ class d3m_tuning(C.Structure):
     _fields_ = [("s1_block", C.c_int32), ("solve_cols", C.c_int32), ("lookahead_tasks", C.c_int32),
                 ("k_block", C.c_int32), ("side_early", C.c_int32), ("k_fuse", C.c_int32),
                 ("panel_rows", C.c_int32), ("solve_seq", C.c_int32), ("solve_narrow", C.c_int32),
-                ("k_overlap", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("k_overlap", C.c_int32), ("solve_chain", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class d3m_bk_out(C.Structure):
@@ -133,6 +134,7 @@ _lib.d3m_probe.argtypes = [_h, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_i
 _lib.d3m_rhs_dipole.argtypes = [_h, C.POINTER(C.c_double), C.c_void_p, C.c_int32, C.c_void_p]
 _lib.d3m_debug_check_schedule.argtypes = [_h, C.c_int32, C.c_char_p, C.c_int64]
 _lib.d3m_debug_check_schedule.restype = C.c_int64
+_lib.d3m_debug_chain_wait_limit.argtypes = [_h, C.c_double]
 _lib.d3m_query.argtypes = [_h, C.POINTER(d3m_info)]
 _lib.d3m_destroy.argtypes = [_h]
 _lib.d3m_destroy.restype = None
@@ -392,6 +394,21 @@ class Solver:
             _check(int(n))
         return int(n), buf.value.decode()
 
+    def check_solve_chain(self, drop_wait=False):
+        """Host simulation of the work-queue K solve sweeps (no GPU): the
+        number of violations found and a description.  drop_wait plants a
+        missing wait into every item."""
+        buf = C.create_string_buffer(8192)
+        n = _lib.d3m_debug_check_schedule(self._handle, 4 | (8 if drop_wait else 0), buf, len(buf))
+        if n < 0:
+            _check(int(n))
+        return int(n), buf.value.decode()
+
+    def set_chain_wait_limit(self, seconds):
+        """Bound of one dependency wait of the work-queue K solve sweeps
+        (seconds; 0 makes every unmet wait run out: failure-path tests)."""
+        _check(_lib.d3m_debug_chain_wait_limit(self._handle, C.c_double(seconds)))
+
     def rhs_dipole(self, pos, moment):
         """Point-dipole loads (impressed currents), one per right-hand side:
         pos [nrhs][3], moment [nrhs][3] complex (current moment I l)."""
@@ -451,7 +468,7 @@ class Solver:
         _check(_lib.d3m_set_graphs(self._handle, int(bool(use_graph))))
 
     TUNING_KEYS = ("s1_block", "solve_cols", "lookahead_tasks", "k_block", "side_early", "k_fuse", "panel_rows",
-                   "solve_seq", "solve_narrow", "k_overlap")
+                   "solve_seq", "solve_narrow", "k_overlap", "solve_chain")
 
     def tuning(self):
         t = d3m_tuning()

@@ -10,7 +10,7 @@ OUT = os.path.join(HERE, "libd3m.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels/factor.hip", "kernels/solve.hip", "solve_noalloc.hip"]
-CXX_SOURCES = ["host/mesh.cpp", "host/decomp.cpp", "host/plan.cpp", "host/plan_mf.cpp", "host/race.cpp", "d3m_api.cpp"]
+CXX_SOURCES = ["host/mesh.cpp", "host/decomp.cpp", "host/plan.cpp", "host/plan_mf.cpp", "host/plan_chain.cpp", "host/race.cpp", "host/chain_sim.cpp", "d3m_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-variable", "-Wno-unused-result"]
 # packed FP32 arithmetic stays off in every device compile

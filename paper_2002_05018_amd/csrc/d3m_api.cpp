@@ -84,6 +84,16 @@ struct d3m_problem {
     int64_t *d_sq_fwd = nullptr, *d_sq_bwd = nullptr;
     AddTask *d_mfadd = nullptr;
     int64_t *d_mfsrc = nullptr;
+    // the two K sweeps of the solve as work queues (tuning solve_chain):
+    // item and wait lists, and d_chain = [queue heads of both sweeps, the
+    // sticky timeout flag, unused, write counts of the forward sweep's K
+    // vector tiles, then of the backward sweep's]
+    ChainItem *d_kc_items[2] = {nullptr, nullptr};
+    ChainWait *d_kc_waits[2] = {nullptr, nullptr};
+    VDiagTask *d_kc_pre[2] = {nullptr, nullptr};
+    unsigned *d_chain = nullptr;
+    uint64_t chain_spin_ticks = 0;  // bound of one dependency wait (wall-clock ticks, 2 s)
+    int chain_clock_khz = 100000;   // rate of the device's wall clock
     unsigned long long *d_disc = nullptr;
     FactorTile *d_lhat_s1 = nullptr, *d_lhat_k = nullptr;
     unsigned long long *d_growth = nullptr;
@@ -322,6 +332,17 @@ int upload_schedules(d3m_problem *h, bool replace) {
     UPS(h->d_lmap, pl.lam_map);
     UPS(h->d_mfadd, pl.mf_add);
     UPS(h->d_mfsrc, pl.mf_src);
+    UPS(h->d_kc_items[0], pl.kc_items[0]);
+    UPS(h->d_kc_items[1], pl.kc_items[1]);
+    UPS(h->d_kc_waits[0], pl.kc_waits[0]);
+    UPS(h->d_kc_waits[1], pl.kc_waits[1]);
+    UPS(h->d_kc_pre[0], pl.kc_pre[0]);
+    UPS(h->d_kc_pre[1], pl.kc_pre[1]);
+    {
+        // queue heads, timeout flag, unused word, write counts of both sweeps
+        const std::vector<unsigned> zero(4 + 2 * (size_t)std::max<i64>(pl.v_tiles_k, 1), 0u);
+        UPS(h->d_chain, zero);
+    }
 #undef UPS
     return D3M_OK;
 }
@@ -353,6 +374,13 @@ int setup_device(d3m_problem *h) {
         UP(h->d_eprob, ep);
     }
     if ((rc = h->zeros(h->d_status, sizeof(int) * (pl.n_status + 1))) != D3M_OK) return rc;
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->opt.device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        h->chain_clock_khz = khz;
+        h->chain_spin_ticks = (uint64_t)khz * 1000ull * 2ull;
+    }
     size_t dr = (size_t)std::max<i64>(pl.d_rows, 1);
     if ((rc = h->zeros(h->D.d, dr * sizeof(double2))) != D3M_OK) return rc;
     if ((rc = h->zeros(h->D.doff, dr * sizeof(double2))) != D3M_OK) return rc;
@@ -800,9 +828,26 @@ int solve_launch_vb(d3m_problem *h, const VBases &vb, const double2 *f, double2 
     else
         for (const auto &st : pl.s1_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
     HIPCHK(launch_vgather_h<T>(vb.p[V_KX], vb.p[V_X], h->d_hmap, pl.v_tiles_k * 64, nrhs, s));
-    for (const auto &st : pl.k_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
-    HIPCHK(launch_fill_zero<T>(vb.p[V_KACC], pl.v_tiles_k * 64 * nrhs, s));
-    for (const auto &st : pl.k_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
+    if (h->tune.solve_chain && pl.chain_ok) {
+        // each K sweep: the diagonal solves no update precedes, then one
+        // work-queue launch over all its update tasks in the level-by-level
+        // order (each carrying the solve of the tile it writes last)
+        unsigned *head = h->d_chain, *err = h->d_chain + 2, *cnt = h->d_chain + 4;
+        const int cols = h->tune.solve_cols;
+        HIPCHK(launch_vchain_reset(head, cnt, 2 * pl.v_tiles_k, s));
+        for (int sw = 0; sw < 2; ++sw) {
+            const bool bwd = sw == 1;
+            if (bwd) HIPCHK(launch_fill_zero<T>(vb.p[V_KACC], pl.v_tiles_k * 64 * nrhs, s));
+            HIPCHK(launch_vdiag<T>(h->d_kc_pre[sw], (int64_t)pl.kc_pre[sw].size(), 1, bwd, b, vb, h->D, nrhs, cols, s));
+            HIPCHK(launch_vchain<T>(h->d_kc_items[sw], (int64_t)pl.kc_items[sw].size(), h->d_kc_waits[sw], h->d_vupd,
+                                    h->d_vpairs, h->d_vdiag, bwd, b, vb, h->D, nrhs, cols, head + sw, err,
+                                    cnt + sw * pl.v_tiles_k, h->chain_spin_ticks, s));
+        }
+    } else {
+        for (const auto &st : pl.k_fwd) if ((rc = solve_step<T>(h, st, b, vb, false, nrhs, s))) return rc;
+        HIPCHK(launch_fill_zero<T>(vb.p[V_KACC], pl.v_tiles_k * 64 * nrhs, s));
+        for (const auto &st : pl.k_bwd) if ((rc = solve_step<T>(h, st, b, vb, true, nrhs, s))) return rc;
+    }
     HIPCHK(launch_vscatter_lam<T>(vb.p[V_X], vb.p[V_KX], h->d_lmap, pl.v_tiles_s1 * 64, nrhs, s));
     if (h->tune.solve_seq)
         HIPCHK(launch_vseq<T>(h->d_vupd, h->d_vfuse, h->d_sq_bwd, h->dc.N, h->d_vpairs, h->d_vdiag, true, b, vb, h->D,
@@ -928,6 +973,20 @@ int copy_discrepancy(d3m_problem *h, int nrhs, double &out, hipStream_t s) {
     return D3M_OK;
 }
 
+// the work-queue K sweeps bound every dependency wait; a wait that ran out
+// leaves the flag set (and the solution wrong): report it once, then clear it
+int chain_check(d3m_problem *h, hipStream_t s) {
+    if (!h->d_chain) return D3M_OK;
+    unsigned flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, h->d_chain + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag == 0) return D3M_OK;
+    const unsigned zero = 0;
+    HIPCHK(hipMemcpyAsync(h->d_chain + 2, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return fail(D3M_EHIP, "a dependency wait of the work-queue K solve sweep timed out (solution invalid)");
+}
+
 // full solve on device buffers (both precisions); optional diagnostics
 int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_solve_info *info, hipStream_t s) {
     const size_t vbytes = sizeof(double2) * (size_t)nrhs * h->mesh.ne;
@@ -947,7 +1006,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
         }
         HIPCHK(hipStreamSynchronize(s));
         h->prof_collect();
-        return D3M_OK;
+        return chain_check(h, s);
     }
     // FP32 factors with FP64 iterative refinement on S E = f
     if ((rc = h->ensure(h->stage_r, vbytes))) return rc;
@@ -1005,6 +1064,7 @@ int solve_device(d3m_problem *h, const double2 *f, double2 *E, int nrhs, d3m_sol
     }
     HIPCHK(hipStreamSynchronize(s));
     h->prof_collect();
+    if ((rc = chain_check(h, s)) != D3M_OK) return rc;
     if (info) {
         info->iterations = it;
         info->converged = ok ? 1 : 0;
@@ -1083,6 +1143,7 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
 // when the handle's options ask for it.
 void make_plan(Plan &pl, const d3m_problem *h, int scope, int s1_block, int k_block, bool k_fuse) {
     build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse);
+    build_solve_chain(pl);
     if (h->opt.k_multifrontal) build_multifrontal(pl, k_block > 0 ? k_block : 2);
     // loads on PEC edges are ignored: their subdomain rows start from zero
     if (h->mesh.n_pec > 0)
@@ -1261,6 +1322,8 @@ int d3m_set_tuning(d3m_handle h, const d3m_tuning *t) {
     if (t->solve_seq != 0 && t->solve_seq != 1) return fail(D3M_EINVAL, "solve_seq must be 0 or 1");
     if (t->solve_narrow < 0) return fail(D3M_EINVAL, "solve_narrow must be >= 0");
     if (t->k_overlap != 0 && t->k_overlap != 1) return fail(D3M_EINVAL, "k_overlap must be 0 or 1");
+    if (t->solve_chain != 0 && t->solve_chain != 1) return fail(D3M_EINVAL, "solve_chain must be 0 or 1");
+    if (t->reserved[0] != 0) return fail(D3M_EINVAL, "reserved tuning fields must be 0");
     const int old_s1 = h->tune.s1_block, old_k = h->tune.k_block, old_f = h->tune.k_fuse;
     h->drop_graphs();
     h->tune = *t;
@@ -1583,7 +1646,23 @@ int d3m_rhs_dipole(d3m_handle h, const double *pos, const d3m_c128 *moment, int3
 
 int64_t d3m_debug_check_schedule(d3m_handle h, int32_t flags, char *report, int64_t report_bytes) {
     if (!h) return fail(D3M_EINVAL, "null handle");
-    if (flags < 0 || flags > 3) return fail(D3M_EINVAL, "flags must be in [0, 3]");
+    if (flags < 0 || flags > 15) return fail(D3M_EINVAL, "flags must be in [0, 15]");
+    if (flags & 4) {
+        std::string rep;
+        int64_t bad = 0;
+        try {
+            bad = check_solve_chain(h->pl, (flags & 8) != 0, rep);
+        } catch (const std::bad_alloc &) {
+            return fail(D3M_ENOMEM, "host allocation failed in the queue simulation");
+        }
+        if (bad < 0) return fail(D3M_EINVAL, rep);
+        if (report && report_bytes > 0) {
+            const size_t n = std::min<size_t>(rep.size(), (size_t)report_bytes - 1);
+            std::memcpy(report, rep.data(), n);
+            report[n] = 0;
+        }
+        return bad;
+    }
     const bool force_side = (flags & 1) != 0;
     ScheduleModel m;
     m.lookahead_tasks = h->tune.lookahead_tasks;
@@ -1607,6 +1686,15 @@ int64_t d3m_debug_check_schedule(d3m_handle h, int32_t flags, char *report, int6
         report[n] = 0;
     }
     return races;
+}
+
+int d3m_debug_chain_wait_limit(d3m_handle h, double seconds) {
+    if (!h) return fail(D3M_EINVAL, "null handle");
+    if (!(seconds >= 0.0 && seconds <= 60.0)) return fail(D3M_EINVAL, "seconds must be in [0, 60]");
+    if (!h->device_ready) return fail(D3M_ESTATE, "handle was set up host-only");
+    h->chain_spin_ticks = (uint64_t)(seconds * 1000.0 * (double)h->chain_clock_khz);
+    h->drop_solve_graphs();  // captured launches hold the old bound
+    return D3M_OK;
 }
 
 int d3m_probe(d3m_handle h, const double *pts, int32_t n, int64_t *edges, double *coef) {

@@ -1,6 +1,7 @@
 // Tile layouts and launch schedules of the factor and solve phases.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "../tasks.hpp"
@@ -113,6 +114,16 @@ struct Plan {
     i64 ku_tiles = 0;                  // tiles of the update-matrix pool
     i64 ku_tiles_total = 0;            // ... without reuse (sum over units)
     double mf_add_bytes = 0.0;         // complex128 bytes moved by the extend-adds of one factorisation
+    // ---- the two sweeps over the factor of -K as work-queue item lists ------
+    // (one launch per sweep; built by build_solve_chain, index 0 forward, 1
+    // backward).  chain_ok is false, with the reason in chain_why, where the
+    // sweeps hold tasks the item form does not cover (diagonal blocks of
+    // several tiles).
+    bool chain_ok = false;
+    std::string chain_why;
+    std::vector<ChainItem> kc_items[2];
+    std::vector<ChainWait> kc_waits[2];
+    std::vector<VDiagTask> kc_pre[2];  // diagonal solves no update precedes: one launch before the queue
     // ---- algorithmic counts -----------------------------------------------
     double flops_s1 = 0.0, flops_s3 = 0.0, flops_update = 0.0;
     double mfma_flops_update = 0.0;    // update-GEMM work as executed on full 64x64x64 tile
@@ -126,6 +137,10 @@ struct Plan {
 
 void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
                 bool k_fuse);
+
+// Builds the work-queue form of the two K sweeps of the solve from the
+// level-by-level schedule (k_fwd, k_bwd, vdiag, vupd, vfuse of build_plan).
+void build_solve_chain(Plan &pl);
 
 // Adds the multifrontal schedule of step 5 to a plan made by build_plan;
 // fronts are amalgamated along elimination-tree chains of at most seg_max

@@ -70,6 +70,20 @@ template <typename T>
 hipError_t launch_vseq(const VUpdTask *tasks, const int64_t *fuse, const int64_t *off, int nsub,
                        const VUpdPair *pairs, const VDiagTask *vdiag, bool bwd, const Bases &b, const VBases &vb,
                        const DArrays &D, int nrhs, int cols, hipStream_t s);
+// a whole sweep over the factor of -K in one launch, from the work-queue item
+// list of build_solve_chain (forward: update mode 0, backward: mode 2; the
+// list's pre-launched diagonal solves must be complete).
+// head: the sweep's queue counter, err: the sticky timeout flag, cnt: one
+// write counter per K vector tile; head and cnt zeroed by launch_vchain_reset
+// before the sweep.  spin_ticks bounds every dependency wait (wall-clock
+// ticks).
+template <typename T>
+hipError_t launch_vchain(const ChainItem *items, int64_t nitem, const ChainWait *waits, const VUpdTask *tasks,
+                         const VUpdPair *pairs, const VDiagTask *vdiag, bool bwd, const Bases &b,
+                         const VBases &vb, const DArrays &D, int nrhs, int cols, unsigned *head, unsigned *err,
+                         unsigned *cnt, uint64_t spin_ticks, hipStream_t s);
+// head[0..1] = 0 and cnt[0..n) = 0 (a kernel, so graphs may hold it)
+hipError_t launch_vchain_reset(unsigned *head, unsigned *cnt, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s);
 template <typename T>

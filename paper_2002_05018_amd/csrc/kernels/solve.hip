@@ -216,18 +216,12 @@ __device__ __forceinline__ void sv_diag(const typename C2T<T>::type (&lf)[16], c
         }
 }
 
+// One one-tile diagonal solve for the right-hand sides c0 .. c0 + ncol - 1,
+// by the whole work-group.
 template <typename T, bool BWD, int NCB>
-__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int64_t ntask, Bases b, VBases vb,
-                                                    DArrays D, int nrhs) {
+__device__ __forceinline__ void vdiag_task(const VDiagTask &tk, const Bases &b, const VBases &vb, const DArrays &D,
+                                           int nrhs, int c0, int ncol, SvSmem<typename C2T<T>::type, NCB> &sm) {
     using T2 = typename C2T<T>::type;
-    __shared__ SvSmem<T2, NCB> sm;
-    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
-    const int64_t item = xcd_task(ntask * nyb);
-    if (item >= ntask * nyb) return;
-    const int64_t task = item / nyb;
-    const VDiagTask tk = tasks[task];
-    const int c0 = (int)(item - task * nyb) * 16 * NCB;
-    const int ncol = min(16 * NCB, nrhs - c0);
     T2 xr[4 * NCB], lf[16];
     if (BWD)
         sv_fetch_x<T2, NCB>(xr, vptr<T2>(vb, tk.v, nrhs), tk.acc >= 0 ? vptr<T2>(vb, tk.acc, nrhs) : nullptr, c0, ncol);
@@ -237,6 +231,19 @@ __global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int6
     sv_put_x<T2, NCB>(sm.xs[0], xr);
     __syncthreads();
     sv_diag<T, BWD, NCB>(lf, tk, c0, ncol, vb, D, nrhs, sm.xs[0], sm.xs[1]);
+}
+
+template <typename T, bool BWD, int NCB>
+__global__ __launch_bounds__(256) void vdiag_kernel(const VDiagTask *tasks, int64_t ntask, Bases b, VBases vb,
+                                                    DArrays D, int nrhs) {
+    using T2 = typename C2T<T>::type;
+    __shared__ SvSmem<T2, NCB> sm;
+    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
+    const int64_t item = xcd_task(ntask * nyb);
+    if (item >= ntask * nyb) return;
+    const int64_t task = item / nyb;
+    const int c0 = (int)(item - task * nyb) * 16 * NCB;
+    vdiag_task<T, BWD, NCB>(tasks[task], b, vb, D, nrhs, c0, min(16 * NCB, nrhs - c0), sm);
 }
 
 // Diagonal blocks of several tiles (blocks larger than 64 factored whole):
@@ -478,6 +485,109 @@ __global__ __launch_bounds__(256, 2) void vseq_kernel(const VUpdTask *tasks, con
         __syncthreads();
         vupd_task<T, MODE, NCB>(tasks[t], fuse[t], pairs, vdiag, b, vb, D, nrhs, c0, ncol, sm);
     }
+}
+
+// A whole sweep over the factor of -K in one launch, from a work queue (the
+// diagonal solves that no update precedes run as a launch of their own
+// before it).  Items (update tasks, each with the diagonal solve of its
+// target when it writes that tile last, times the column blocks of the
+// right-hand sides) are
+// taken in the sweep's sequential order from one global counter (head), so
+// an item waits only for items taken before it by work-groups that are
+// running: the first unfinished item always has its inputs, whatever the
+// number of resident work-groups, and the queue drains.  cnt[t] counts the
+// completed writes of vector tile t (one per item and column block); an item
+// waits until every tile in its wait list has the writes that precede it in
+// the sequential order, runs, and adds one to the count of the tile it
+// wrote.  The counts are polled with relaxed loads; a satisfied wait ends
+// with one agent-scope acquire (an invalidation of the L1 and L2 the
+// work-group reads through), and the count goes up with an agent-scope
+// release (an L2 write-back) once every wave's stores are complete: the
+// XCDs have separate L2 caches.  Every wait is bounded by spin_ticks of the
+// constant-rate wall clock: on expiry the work-group sets *err, and every
+// work-group leaves at its next look at *err, so the launch always ends; the
+// host reports the flag.
+// s_waitcnt immediate of vmcnt(0) alone (GFX9 encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4, lgkmcnt 11:8 left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
+
+template <typename T, int MODE, int NCB>
+__global__ __launch_bounds__(256, 2) void vchain_kernel(const ChainItem *items, int64_t nitem, const ChainWait *waits,
+                                                     const VUpdTask *tasks, const VUpdPair *pairs,
+                                                     const VDiagTask *vdiag, Bases b,
+                                                     VBases vb, DArrays D, int nrhs, unsigned *head, unsigned *err,
+                                                     unsigned *cnt, uint64_t spin_ticks) {
+    using T2 = typename C2T<T>::type;
+    __shared__ SvSmem<T2, NCB> sm;
+    __shared__ int64_t s_item;
+    __shared__ int s_ok;
+    const int nyb = (nrhs + 16 * NCB - 1) / (16 * NCB);
+    const int64_t total = nitem * nyb;
+    for (;;) {
+        __syncthreads();  // the previous item is done with LDS and s_item
+        if (threadIdx.x == 0) {
+            const unsigned e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_item = e ? total
+                       : (int64_t)__hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        // wave-uniform (scalar registers): the item's task data then comes
+        // through scalar loads, as in the one-launch-per-step kernels
+        const int64_t it = rdlane64(s_item, 0);
+        if (it >= total) return;
+        const int64_t k = it / nyb;
+        const int c0 = (int)(it - k * nyb) * 16 * NCB;
+        const ChainItem ci = items[k];
+        if (threadIdx.x < 64) {
+            bool ok = true;
+            for (int w = threadIdx.x; ok && w < ci.nw; w += 64) {
+                const ChainWait cw = waits[ci.w0 + w];
+                const unsigned need = (unsigned)cw.writes * (unsigned)nyb;
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(cnt + cw.tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        wall_clock64() - t0 > spin_ticks) {
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            const bool all = __all(ok ? 1 : 0) != 0;
+            if (threadIdx.x == 0) s_ok = all ? 1 : 0;
+            // acquire once for the work-group: its waves share this compute
+            // unit's L1 and this XCD's L2, and the invalidation completes
+            // before the barrier lets the other waves load
+            if (all) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            }
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_ok)) return;
+        const int ncol = min(16 * NCB, nrhs - c0);
+        vupd_task<T, MODE, NCB>(tasks[ci.idx], ci.fz, pairs, vdiag, b, vb, D, nrhs, c0, ncol, sm);
+        // every wave's stores complete in L2 before the barrier; then one L2
+        // write-back for the work-group, complete before the count goes up
+        // (an explicit wait: the release sequence's own wait is dropped by
+        // the compiler when no store of this wave is outstanding)
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (threadIdx.x == 0 && ci.sig >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            __hip_atomic_fetch_add(cnt + ci.sig, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// zeroes the write counts of both K sweeps and their queue heads (not the
+// error flag, which stays set until the host has read it)
+__global__ void vchain_reset_kernel(unsigned *head, unsigned *cnt, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) cnt[idx] = 0;
+    if (idx < 2) head[idx] = 0;
 }
 
 // XK[R] = X[h0(R)] + X[h1(R)]  (the two subdomain copies of each multiplier row)
@@ -837,6 +947,56 @@ hipError_t launch_vupd(const VUpdTask *tasks, const int64_t *fuse, int64_t ntask
     else launch_vupd_ncb<T, 2>(tasks, fuse, ntask, pairs, vdiag, mode, b, vb, D, nrhs, s);
     return hipGetLastError();
 }
+hipError_t launch_vchain_reset(unsigned *head, unsigned *cnt, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(vchain_reset_kernel, g1(std::max<int64_t>(n, 2)), dim3(256), 0, s, head, cnt, n);
+    return hipGetLastError();
+}
+
+// work-groups of a work-queue sweep: as many as can be resident at once (the
+// queue does not need them all resident; more would only wait for a slot),
+// at most one per item
+template <typename K>
+unsigned chain_grid(K kernel, int64_t items) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) return 0;
+    const int64_t g = std::min<int64_t>((int64_t)std::max(per, 1) * std::max(cus, 1), items);
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+
+template <typename T, int MODE, int NCB>
+hipError_t launch_vchain_ncb(const ChainItem *items, int64_t nitem, const ChainWait *waits, const VUpdTask *tasks,
+                             const VUpdPair *pairs, const VDiagTask *vdiag, const Bases &b,
+                             const VBases &vb, const DArrays &D, int nrhs, unsigned *head, unsigned *err,
+                             unsigned *cnt, uint64_t spin_ticks, hipStream_t s) {
+    auto kern = vchain_kernel<T, MODE, NCB>;
+    const int64_t total = nitem * ((nrhs + 16 * NCB - 1) / (16 * NCB));
+    const unsigned grid = chain_grid(kern, total);
+    if (grid == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, items, nitem, waits, tasks, pairs, vdiag, b, vb, D, nrhs,
+                       head, err, cnt, spin_ticks);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vchain(const ChainItem *items, int64_t nitem, const ChainWait *waits, const VUpdTask *tasks,
+                         const VUpdPair *pairs, const VDiagTask *vdiag, bool bwd, const Bases &b,
+                         const VBases &vb, const DArrays &D, int nrhs, int cols, unsigned *head, unsigned *err,
+                         unsigned *cnt, uint64_t spin_ticks, hipStream_t s) {
+    if (nitem <= 0) return hipSuccess;
+    const bool one = sv_ncb(nrhs, cols) == 1;
+    if (bwd)
+        return one ? launch_vchain_ncb<T, 2, 1>(items, nitem, waits, tasks, pairs, vdiag, b, vb, D, nrhs, head,
+                                                err, cnt, spin_ticks, s)
+                   : launch_vchain_ncb<T, 2, 2>(items, nitem, waits, tasks, pairs, vdiag, b, vb, D, nrhs, head,
+                                                err, cnt, spin_ticks, s);
+    return one ? launch_vchain_ncb<T, 0, 1>(items, nitem, waits, tasks, pairs, vdiag, b, vb, D, nrhs, head, err,
+                                            cnt, spin_ticks, s)
+               : launch_vchain_ncb<T, 0, 2>(items, nitem, waits, tasks, pairs, vdiag, b, vb, D, nrhs, head, err,
+                                            cnt, spin_ticks, s);
+}
+
 template <typename T>
 hipError_t launch_vgather_h(void *XK, const void *X, const int64_t *hmap, int64_t nrows_k, int nrhs, hipStream_t s) {
     using T2 = typename C2T<T>::type;
@@ -912,6 +1072,10 @@ hipError_t launch_adjoint_grad(double *grad, const double2 *w, const double2 *E,
     template hipError_t launch_vseq<T>(const VUpdTask *, const int64_t *, const int64_t *, int, const VUpdPair *,  \
                                        const VDiagTask *, bool, const Bases &, const VBases &, const DArrays &, int, \
                                        int, hipStream_t);                                                         \
+    template hipError_t launch_vchain<T>(const ChainItem *, int64_t, const ChainWait *, const VUpdTask *,         \
+                                         const VUpdPair *, const VDiagTask *, bool, const Bases &,                  \
+                                         const VBases &, const DArrays &, int, int, unsigned *, unsigned *,       \
+                                         unsigned *, uint64_t, hipStream_t);                                      \
     template hipError_t launch_vgather_h<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);     \
     template hipError_t launch_vscatter_lam<T>(void *, const void *, const int64_t *, int64_t, int, hipStream_t);  \
     template hipError_t launch_vcollect<T>(double2 *, const void *, const int64_t *, int64_t, int, bool,           \

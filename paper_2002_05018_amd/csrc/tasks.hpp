@@ -114,4 +114,20 @@ struct VUpdPair {
     int64_t l, src;
 };
 
+// One item of a sweep over the factor of -K run as a single launch: update
+// task vupd[idx], then diagonal solve vdiag[fz] if fz >= 0 (the solve of the
+// item's target tile, which this item writes last).  Before it runs, vector
+// tile waits[i].tile must have received waits[i].writes completed writes (per
+// column block), for i in [w0, w0 + nw); afterwards the write count of tile
+// sig goes up by one.
+struct ChainItem {
+    int32_t idx;
+    int32_t w0, nw;
+    int32_t sig;
+    int32_t fz, pad;
+};
+struct ChainWait {
+    int32_t tile, writes;
+};
+
 }  // namespace d3m

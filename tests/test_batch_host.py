@@ -62,18 +62,18 @@ def test_planewave_loads_per_problem(batch):
 def test_tuning_validates_and_replans(batch):
     probs, s, singles = batch
     s.set_tuning(s1_block=4, lookahead_tasks=100, solve_cols=16, k_block=3, panel_rows=16,
-                 solve_seq=1, solve_narrow=512, k_overlap=1)
+                 solve_seq=1, solve_narrow=512, k_overlap=1, solve_chain=1)
     assert s.tuning() == {"s1_block": 4, "solve_cols": 16, "lookahead_tasks": 100, "k_block": 3,
                           "side_early": 0, "k_fuse": 0, "panel_rows": 16,
-                          "solve_seq": 1, "solve_narrow": 512, "k_overlap": 1}
+                          "solve_seq": 1, "solve_narrow": 512, "k_overlap": 1, "solve_chain": 1}
     assert s.query()["array_bytes"] == s.info["array_bytes"]  # layout unchanged
     for bad in ({"s1_block": 17}, {"solve_cols": 8}, {"lookahead_tasks": -1}, {"k_block": 17},
                 {"side_early": 2}, {"k_fuse": 2}, {"panel_rows": 32}, {"solve_seq": 2},
-                {"solve_narrow": -1}, {"k_overlap": 2}):
+                {"solve_narrow": -1}, {"k_overlap": 2}, {"solve_chain": 2}):
         with pytest.raises(D3MError):
             s.set_tuning(**bad)
     s.set_tuning(s1_block=0, lookahead_tasks=0, solve_cols=0, k_block=0, panel_rows=0,
-                 solve_seq=0, solve_narrow=0, k_overlap=0)
+                 solve_seq=0, solve_narrow=0, k_overlap=0, solve_chain=0)
 
 
 def test_empty_batch_rejected():
