@@ -132,7 +132,15 @@ typedef struct {
                              (extend-add).  Same factors up to the order of
                              rounding; needs an extra pool of update
                              matrices (d3m_info.mf_pool_bytes)               */
-    int32_t reserved[3];
+    int32_t s1_order;     /* row order of the edge part of each subdomain
+                             matrix M_d in step 1: 0 (default) interior then
+                             interface edges, each by global id (A_d
+                             banded); 1 nested dissection of all its edge
+                             rows (geometric bisection, separators after
+                             both sides), the multiplier rows last either
+                             way; the tile pattern follows the fill of the
+                             order chosen                                    */
+    int32_t reserved[2];
 } d3m_options;
 
 typedef struct {

@@ -73,7 +73,7 @@ class d3m_options(C.Structure):
                 ("ir_max_iter", C.c_int32), ("profile", C.c_int32), ("ir_tol", C.c_double),
                 ("use_graph", C.c_int32), ("device", C.c_int32), ("pivot_scope", C.c_int32), ("s1_block", C.c_int32),
                 ("pivot_fallback", C.c_int32), ("growth_limit_log10", C.c_int32), ("k_multifrontal", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("s1_order", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class d3m_info(C.Structure):
@@ -184,7 +184,7 @@ def _stream_handle(stream):
 
 def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol=1e-10, ir_max_iter=10,
              pivot_scope=0, s1_block=0, use_graph=False, pivot_fallback=True, growth_limit_log10=0,
-             multifrontal=False):
+             multifrontal=False, s1_order=0):
     opt = d3m_options()
     _lib.d3m_default_options(C.byref(opt))
     opt.host_only = int(host_only)
@@ -200,6 +200,7 @@ def _options(*, host_only=False, profile=False, device=0, quad_points=12, ir_tol
     opt.pivot_fallback = int(bool(pivot_fallback))
     opt.growth_limit_log10 = int(growth_limit_log10)
     opt.k_multifrontal = int(bool(multifrontal))
+    opt.s1_order = int(s1_order)
     return opt
 
 

@@ -1203,13 +1203,14 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
     if (h->opt.pivot_scope != 0 && h->opt.pivot_scope != 1) return fail(D3M_EINVAL, "pivot_scope must be 0 or 1");
     if (h->opt.k_multifrontal != 0 && h->opt.k_multifrontal != 1)
         return fail(D3M_EINVAL, "k_multifrontal must be 0 or 1");
+    if (h->opt.s1_order != 0 && h->opt.s1_order != 1) return fail(D3M_EINVAL, "s1_order must be 0 or 1");
     try {
         build_mesh(h->mesh, nv, xyz, nt, tets);
         mark_pec(h->mesh, npec, pec);
         h->k = k;
         h->alpha = cplx(alpha.re, alpha.im);
         h->eps.assign(eps_r, eps_r + nt);
-        build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r);
+        build_decomposition(h->dc, h->mesh, part, k, h->alpha, eps_r, h->opt.s1_order);
         if (!sub_group.empty() && (int)sub_group.size() != h->dc.N)
             throw Error{-1, "a problem of the batch has an empty subdomain"};
         order_blocks(h->bo, h->dc, h->mesh, sub_group);

@@ -48,8 +48,111 @@ struct Dsu {
 
 }  // namespace
 
+namespace {
+
+// Nested-dissection order of the edge rows of one subdomain (interior and
+// interface edges alike; the multiplier rows stay last), as groups in
+// elimination order.  Two edges are neighbours when they share a
+// tetrahedron of the subdomain (the pattern of A_d).  A region of more than
+// `leaf` edges is cut at the median of its edge midpoints along its longest
+// extent; the lower side's edges that neighbour the upper side form the
+// separator, which follows both sides, so the two sides eliminate
+// independently and fill stays inside fronts.  Each leaf and each separator
+// is one group, by increasing global id.
+std::vector<std::vector<i64>> nested_dissection(const Mesh &m, const std::vector<i32> &part, int d, const std::vector<i64> &edges,
+                                   const std::vector<i64> &tets_of_d, int leaf) {
+    const i64 n = (i64)edges.size();
+    std::vector<i64> sorted(edges);
+    std::sort(sorted.begin(), sorted.end());
+    auto local = [&](i64 e) { return (i64)(std::lower_bound(sorted.begin(), sorted.end(), e) - sorted.begin()); };
+    // neighbour lists (CSR) over local indices
+    std::vector<std::vector<i64>> nb(n);
+    for (i64 t : tets_of_d) {
+        if (part[t] != d) continue;
+        i64 le[6];
+        for (int a = 0; a < 6; ++a) le[a] = local(m.tet_edges[6 * t + a]);
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b)
+                if (a != b) nb[le[a]].push_back(le[b]);
+    }
+    for (auto &v : nb) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    std::vector<double> mid(3 * n);
+    for (i64 i = 0; i < n; ++i) {
+        const i64 e = sorted[i], a = m.edges[2 * e], b = m.edges[2 * e + 1];
+        for (int c = 0; c < 3; ++c) mid[3 * i + c] = 0.5 * (m.xyz[3 * a + c] + m.xyz[3 * b + c]);
+    }
+    std::vector<std::vector<i64>> out;
+    i64 placed = 0;
+    std::vector<char> side(n, 0);  // 2: upper side of the current cut
+    // regions are processed depth first: a region pushes (separator marker,
+    // upper, lower) so that lower, upper and then the separator are emitted
+    struct Item { std::vector<i64> r; bool emit; };
+    std::vector<Item> work;
+    {
+        std::vector<i64> all(n);
+        for (i64 i = 0; i < n; ++i) all[i] = i;
+        work.push_back({all, false});
+    }
+    while (!work.empty()) {
+        Item it = std::move(work.back());
+        work.pop_back();
+        std::vector<i64> &r = it.r;
+        if (it.emit || (i64)r.size() <= leaf) {
+            if (r.empty()) continue;
+            std::sort(r.begin(), r.end());
+            out.emplace_back();
+            for (i64 i : r) out.back().push_back(sorted[i]);
+            placed += (i64)r.size();
+            continue;
+        }
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (i64 i : r)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::min(lo[c], mid[3 * i + c]);
+                hi[c] = std::max(hi[c], mid[3 * i + c]);
+            }
+        int ax = 0;
+        for (int c = 1; c < 3; ++c)
+            if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+        std::vector<double> v;
+        v.reserve(r.size());
+        for (i64 i : r) v.push_back(mid[3 * i + ax]);
+        std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+        const double cut = v[v.size() / 2];
+        std::vector<i64> lower, upper, sep;
+        for (i64 i : r) {
+            const bool up = mid[3 * i + ax] >= cut;
+            side[i] = up ? 2 : 1;
+            (up ? upper : lower).push_back(i);
+        }
+        if (lower.empty() || upper.empty()) {
+            for (i64 i : r) side[i] = 0;
+            work.push_back({r, true});
+            continue;
+        }
+        std::vector<i64> lower_in;
+        for (i64 i : lower) {
+            bool touches = false;
+            for (i64 j : nb[i])
+                if (side[j] == 2) { touches = true; break; }
+            (touches ? sep : lower_in).push_back(i);
+        }
+        for (i64 i : r) side[i] = 0;
+        work.push_back({sep, true});
+        work.push_back({upper, false});
+        work.push_back({lower_in, false});
+    }
+    if (placed != n) throw Error{-1, "internal: nested dissection lost edges"};
+    return out;
+}
+
+}  // namespace
+
 void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
-                         cplx alpha, const double *eps) {
+                         cplx alpha, const double *eps, int s1_order) {
     if (!(k > 0.0)) throw Error{-1, "k must be positive"};
     dc.part.assign(part, part + m.nt);
     int N = 0;
@@ -94,9 +197,12 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
     }
 
     // subdomain rows: [interior | interface], each sorted by global id
+    // (s1_order 0), or all edge rows in nested-dissection order (1)
     dc.sub.assign(N, Subdomain());
     {
-        std::vector<std::vector<i64>> edges_of(N);
+        std::vector<std::vector<i64>> edges_of(N), tets_of(N);
+        if (s1_order == 1)
+            for (i64 t = 0; t < m.nt; ++t) tets_of[part[t]].push_back(t);
         for (i64 e = 0; e < m.ne; ++e)
             for (i64 s = dc.sub_ptr[e]; s < dc.sub_ptr[e + 1]; ++s) edges_of[dc.sub_list[s]].push_back(e);
         for (int d = 0; d < N; ++d) {
@@ -106,10 +212,21 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
             S.nI = (i64)I.size();
             S.edges = I;
             S.edges.insert(S.edges.end(), B.begin(), B.end());
+            if (s1_order == 1) {
+                // every group starts a tile: rows of different groups never
+                // share a tile, so the tile pattern keeps the dissection's
+                // fill (padding rows: -1, identity, no load)
+                S.edges.clear();
+                for (const auto &g : nested_dissection(m, dc.part, d, edges_of[d], tets_of[d], kNdLeaf)) {
+                    S.edges.insert(S.edges.end(), g.begin(), g.end());
+                    while (S.edges.size() % TILE) S.edges.push_back(-1);
+                }
+            }
             S.n = (i64)S.edges.size();
             S.sorted = edges_of[d];  // already increasing
-            S.sorted_pos.resize(S.n);
+            S.sorted_pos.resize(S.sorted.size());
             for (i64 r = 0; r < S.n; ++r) {
+                if (S.edges[r] < 0) continue;
                 auto it = std::lower_bound(S.sorted.begin(), S.sorted.end(), S.edges[r]);
                 S.sorted_pos[it - S.sorted.begin()] = (i32)r;
             }
@@ -210,7 +327,7 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
     };
     for (int d = 0; d < N; ++d)
         for (i64 r = 0; r < dc.sub[d].n; ++r)
-            if (is_pec(dc.sub[d].edges[r])) statc[d].push_back({{r, r}, cplx(1.0, 0.0)});
+            if (dc.sub[d].edges[r] < 0 || is_pec(dc.sub[d].edges[r])) statc[d].push_back({{r, r}, cplx(1.0, 0.0)});
     const cplx jk(0.0, k);
     for (i64 f : dc.bface) add_face(part[m.face_tet[2 * f]], f, jk);
     for (size_t i = 0; i < dc.iface.size(); ++i) {

@@ -536,7 +536,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         const Subdomain &S = dc.sub[d];
         for (i64 r = 0; r < S.n; ++r) {
             i64 e = S.edges[r];
-            if (dc.owner[e] == d) pl.split_map[pl.vs1[d] * TILE + r] = e;
+            if (e >= 0 && dc.owner[e] == d) pl.split_map[pl.vs1[d] * TILE + r] = e;
         }
     }
     pl.collect_map.assign(dc.owner.size(), -1);
@@ -549,7 +549,7 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         const Subdomain &S = dc.sub[d];
         for (i64 r = 0; r < S.n; ++r) {
             const i64 e = S.edges[r];
-            if (dc.owner[e] != d) pl.copy_map[pl.vs1[d] * TILE + r] = pl.collect_map[e];
+            if (e >= 0 && dc.owner[e] != d) pl.copy_map[pl.vs1[d] * TILE + r] = pl.collect_map[e];
         }
     }
     // multiplier rows: K vector row <-> the two subdomain copies

@@ -66,7 +66,8 @@ struct Subdomain {
     i64 n = 0;       // rows of the E part (edges of the subdomain)
     i64 nI = 0;      // interior edges (in one subdomain only)
     i64 m = 0;       // LM rows (multipliers touching the subdomain)
-    std::vector<i64> edges;        // [n] global edge of each row, [I | B]
+    std::vector<i64> edges;        // [n] global edge of each row, [I | B] (s1_order 0) or
+                                   // nested dissection with -1 padding rows (1)
     std::vector<i64> sorted;       // global edges sorted (lookup)
     std::vector<i32> sorted_pos;   // row of sorted[i]
     std::vector<i32> blocks;       // canonical blocks touching d, sorted
@@ -100,8 +101,11 @@ struct Decomp {
     int nblk = 0;
 };
 
+// s1_order: 0 rows of each subdomain [interior | interface] by global id
+// (A_d banded), 1 all edge rows in nested-dissection order
 void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
-                         cplx alpha, const double *eps);
+                         cplx alpha, const double *eps, int s1_order = 0);
+constexpr int kNdLeaf = 192;  // largest region of the dissection left uncut (edges)
 // Recompute the A_d values for new eps (same pattern).
 void reassemble_values(Decomp &dc, const Mesh &m, double k, const double *eps);
 
