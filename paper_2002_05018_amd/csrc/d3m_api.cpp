@@ -1142,7 +1142,7 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
 // The plan of a handle: build_plan, then the multifrontal schedule of step 5
 // when the handle's options ask for it.
 void make_plan(Plan &pl, const d3m_problem *h, int scope, int s1_block, int k_block, bool k_fuse) {
-    build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse);
+    build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse, h->opt.s1_order == 1);
     build_solve_chain(pl);
     if (h->opt.k_multifrontal) build_multifrontal(pl, k_block > 0 ? k_block : 2);
     // loads on PEC edges are ignored: their subdomain rows start from zero

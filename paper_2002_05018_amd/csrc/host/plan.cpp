@@ -24,7 +24,7 @@ inline int tile_rows(i64 total, int t) { return (int)std::min<i64>(TILE, total -
 }  // namespace
 
 void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
-                bool k_fuse) {
+                bool k_fuse, bool s1_tree) {
     const int S1_BLOCK = std::max(1, std::min(16, s1_block > 0 ? s1_block : 2));
     const int K_BLOCK = std::max(1, std::min(16, k_block > 0 ? k_block : 2));
     const int N = dc.N;
@@ -192,7 +192,107 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     };
 
     // --------------------------------------------- step 1 (subdomain) plan --
-    for (int j = 0; j < maxTE; ++j) {
+    if (s1_tree) {
+        // Steps by level of the tile elimination tree of every M_d (parent of
+        // tile column j: the first eliminated row tile below it that is
+        // structurally nonzero): the columns of one level are independent
+        // (none lies in another's structure), so they factor in one step,
+        // and each target tile gathers the pairs of all of its step's
+        // columns in one task.  With a nested-dissection row order the
+        // subtrees of the dissection run side by side; targets in columns of
+        // the next level go first (the next step's pivots need them), the
+        // rest may run on the look-ahead stream.
+        std::vector<std::vector<int>> lev(N);
+        int nl = 0;
+        for (int d = 0; d < N; ++d) {
+            lev[d].assign(pl.TE[d], 0);
+            for (int j = 0; j < pl.TE[d]; ++j) {
+                int par = -1;
+                for (int a = j + 1; a < pl.TE[d] && par < 0; ++a)
+                    if (nz[d][a][j]) par = a;
+                if (par >= 0) lev[d][par] = std::max(lev[d][par], lev[d][j] + 1);
+                nl = std::max(nl, lev[d][j] + 1);
+            }
+        }
+        for (int L = 0; L < nl; ++L) {
+            FactorStep st;
+            st.bk0 = (i64)pl.bk.size();
+            for (int d = 0; d < N; ++d)
+                for (int j = 0; j < pl.TE[d]; ++j) {
+                    if (lev[d][j] != L) continue;
+                    BkTask t{};
+                    t.a = t.l = E(ARR_M, mslot(d, j, j));
+                    t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+                    t.drow = pl.drow_s1[d] + (i64)j * TILE;
+                    t.n = mrows(d, j);
+                    t.ldt = 0;
+                    t.status = (int)pl.bk.size();
+                    pl.bk.push_back(t);
+                    st.bk_maxn = std::max(st.bk_maxn, t.n);
+                    pl.flops_s1 += 8.0 * t.n * (double)t.n * t.n / 6.0;
+                }
+            st.nbk = (i64)pl.bk.size() - st.bk0;
+            st.pan0 = (i64)pl.gemm.size();
+            st.sc0 = (i64)pl.scale.size();
+            for (int d = 0; d < N; ++d)
+                for (int j = 0; j < pl.TE[d]; ++j) {
+                    if (lev[d][j] != L) continue;
+                    const int w = mrows(d, j);
+                    for (int a = j + 1; a < pl.T[d]; ++a) {
+                        if (!nz[d][a][j]) continue;
+                        pl.gemm.push_back({E(ARR_MX, mslot(d, a, j)), (int32_t)pl.pairs.size(), 1});
+                        pl.pairs.push_back({E(ARR_M, mslot(d, a, j)), E(ARR_TT, pl.tt_s1[d] + j)});
+                        ScaleTask sc{};
+                        sc.x = E(ARR_MX, mslot(d, a, j));
+                        sc.w = E(ARR_M, mslot(d, a, j));
+                        sc.xprev = sc.xnext = -1;
+                        sc.drow = pl.drow_s1[d] + (i64)j * TILE;
+                        sc.ncols = w;
+                        pl.scale.push_back(sc);
+                        const double pf = 8.0 * mrows(d, a) * (double)w * w / 2.0;
+                        st.pan_flops += pf;
+                        pl.flops_s1 += pf;
+                    }
+                }
+            st.npan = (i64)pl.gemm.size() - st.pan0;
+            st.nsc = (i64)pl.scale.size() - st.sc0;
+            st.fused_scale = st.npan == st.nsc;
+            st.up0 = (i64)pl.gemm.size();
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int d = 0; d < N; ++d) {
+                    std::vector<int> cols;
+                    for (int j = 0; j < pl.TE[d]; ++j)
+                        if (lev[d][j] == L) cols.push_back(j);
+                    if (cols.empty()) continue;
+                    for (int b = cols.front() + 1; b < pl.T[d]; ++b) {
+                        const bool crit = b < pl.TE[d] && lev[d][b] == L + 1;
+                        if (crit != (pass == 0)) continue;
+                        for (int a = b; a < pl.T[d]; ++a) {
+                            GemmTask g{E(ARR_M, 0), (int32_t)pl.pairs.size(), 0};
+                            const int ra = mrows(d, a), rb = mrows(d, b);
+                            for (int j : cols) {
+                                if (j >= b || !nz[d][a][j] || !nz[d][b][j]) continue;
+                                pl.pairs.push_back({E(ARR_MX, mslot(d, a, j)), E(ARR_M, mslot(d, b, j))});
+                                ++g.np;
+                                const double f = 8.0 * mrows(d, j) * (a == b ? ra * (ra + 1) / 2.0 : (double)ra * rb);
+                                st.up_flops += f;
+                                if (pass == 0) st.crit_flops += f;
+                            }
+                            if (g.np == 0) continue;
+                            g.c = E(ARR_M, mslot(d, a, b));
+                            pl.gemm.push_back(g);
+                        }
+                    }
+                }
+                if (pass == 0) st.ncrit = (i64)pl.gemm.size() - st.up0;
+            }
+            st.nup = (i64)pl.gemm.size() - st.up0;
+            pl.flops_s1 += st.up_flops;
+            pl.flops_update += st.up_flops;
+            pl.s1_steps.push_back(st);
+        }
+    }
+    for (int j = 0; j < maxTE && !s1_tree; ++j) {
         FactorStep st;
         st.bk0 = (i64)pl.bk.size();
         for (int d = 0; d < N; ++d) {

@@ -135,8 +135,10 @@ struct Plan {
     i64 factor_entries = 0;
 };
 
+// s1_tree: step 1 by levels of each subdomain's tile elimination tree (for
+// nested-dissection row orders) instead of one tile column per step
 void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, int s1_block, int k_block,
-                bool k_fuse);
+                bool k_fuse, bool s1_tree = false);
 
 // Builds the work-queue form of the two K sweeps of the solve from the
 // level-by-level schedule (k_fwd, k_bwd, vdiag, vupd, vfuse of build_plan).
