@@ -33,9 +33,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="4", choices=["1", "2", "3", "4", "5", "pec"],
-                    help="workload: configurations 1-5, or pec (24^3 hexes with two PEC plates, plane waves "
-                         "and point dipoles)")
+    ap.add_argument("--config", default="4", choices=["1", "2", "3", "4", "5", "pec", "big"],
+                    help="workload: configurations 1-5, pec (24^3 hexes with two PEC plates, plane waves "
+                         "and point dipoles) or big (32^3 hexes in 2x2x2 subdomains of 16^3 hexes, the "
+                         "batch workload's largest subdomains)")
+    ap.add_argument("--s1-order", type=int, default=0, choices=[0, 1],
+                    help="row order of the subdomain matrices: 0 banded (default), 1 nested dissection "
+                         "(step 1 by levels of the dissection tree; for large subdomains)")
     ap.add_argument("--batch-count", type=int, default=32, help="problems of the configuration 3 batch")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--multifrontal", action="store_true",
@@ -251,7 +255,8 @@ def error_vs_oracle(E, cfg):
     """Largest over right-hand sides of max |E - E_oracle| / max |E_oracle|
     at the sampled edges of the committed oracle fixture (None without one)."""
     import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", "fullsize_pec.npz" if cfg == "pec" else f"fullsize_config{cfg}.npz")
+    path = os.path.join(ROOT, "tests", "golden",
+                        f"fullsize_{cfg}.npz" if cfg in ("pec", "big") else f"fullsize_config{cfg}.npz")
     if not os.path.exists(path):
         return None
     with np.load(path, allow_pickle=False) as z:
@@ -348,7 +353,7 @@ def _roofline(up, info, steps, prec, traffic):
 
 def main():
     args = parse()
-    args.config = args.config if args.config == "pec" else int(args.config)
+    args.config = args.config if args.config in ("pec", "big") else int(args.config)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "layout of this path is a design note, not a runnable configuration", file=sys.stderr)
@@ -365,12 +370,13 @@ def main():
     import workloads as W
     from paper_2002_05018_amd import FP32_IR, FP64, Solver
 
-    prob = W.make_pec_config() if args.config == "pec" else W.make_config(args.config)
+    prob = {"pec": W.make_pec_config, "big": W.make_large_subdomain_config}.get(
+        args.config, lambda: W.make_config(args.config))()
     t0 = time.perf_counter()
     # timed steps time only the update GEMM launches (HIP events on their
     # streams); a separate untimed pass with every kernel group timed gives
     # the phase breakdown
-    solver = Solver.from_problem(prob, profile=1, multifrontal=args.multifrontal)
+    solver = Solver.from_problem(prob, profile=1, multifrontal=args.multifrontal, s1_order=args.s1_order)
     setup_s = time.perf_counter() - t0
     info = solver.info
     f_host = solver.rhs_planewave(prob.dirs, prob.pols)
@@ -406,6 +412,8 @@ def main():
     solve_alg = info["solve_bytes"] + info["solve_vector_bytes"] * nrhs
     cfg_name = {"pec": "24^3 hexes (102,024 edges), 4x4x4 box subdomains, two PEC plates, 4 plane-wave and "
                        "4 point-dipole RHS",
+                "big": "32^3 hexes (238,688 edges), 2x2x2 box subdomains of 16^3 hexes (31,024 edges each), "
+                       "16 plane-wave RHS",
                 2: "24^3 hexes (102,024 edges), 4x4x4 box subdomains, 8 plane-wave RHS",
                 4: "48^3 hexes (795,024 edges), 8x8x8 box subdomains, 32 plane-wave RHS",
                 5: "32^3 hexes (238,688 edges), 4x4x4 box subdomains, dielectric sphere, 4 plane-wave RHS",
@@ -428,9 +436,10 @@ def main():
                                f"to 1e-10 side by side",
                    "n_edges": info["n_edges"], "n_lm": info["n_lm"], "n_blocks": info["n_blocks"],
                    "n_subdomains": info["n_subdomains"], "nrhs": nrhs, "precision": "fp64",
-                   "step5": "multifrontal" if args.multifrontal else "right-looking"},
+                   "step5": "multifrontal" if args.multifrontal else "right-looking",
+                   "step1_rows": "nested dissection" if args.s1_order == 1 else "banded"},
         "roofline": _roofline(up, info, args.steps, "c128",
-                              None if args.multifrontal else measured_traffic(args.config, "fp64")),
+                              None if args.multifrontal or args.s1_order else measured_traffic(args.config, "fp64")),
         "phases_ms_per_step": dict(phases, note="separate untimed pass with every kernel group timed "
                                                 "(the two streams overlap, so phases do not add up)"),
         "unknowns_per_s": info["n_edges"] / (ms / 1e3),
@@ -470,7 +479,7 @@ def main():
                              "max_rel_diff_vs_fp64": diff,
                              "speedup_vs_fp64": ms / ms32,
                              "roofline": _roofline(up32, info32, args.steps, "c64",
-                                                   None if args.multifrontal
+                                                   None if args.multifrontal or args.s1_order
                                                    else measured_traffic(args.config, "fp32_ir"))}
     if args.multifrontal:
         result["multifrontal"] = {"pool_bytes": info["mf_pool_bytes"], "update_matrix_bytes": info["mf_update_bytes"],

@@ -186,7 +186,8 @@ typedef struct {
     int32_t pivot_fallbacks;  /* factorisations redone with the whole-block
                                  scope (options.pivot_fallback)               */
     int32_t k_multifrontal;   /* 1 when step 5 runs in multifrontal form      */
-    int32_t pad0;
+    int32_t s1_order;         /* row order of the subdomain matrices
+                                 (options.s1_order)                           */
     double mf_pool_bytes;     /* device bytes of the update-matrix pool of one
                                  precision (complex128; half for FP32_IR), 0
                                  in the right-looking form                    */

@@ -86,7 +86,7 @@ class d3m_info(C.Structure):
                 ("n_problems", C.c_int32), ("array_bytes", C.c_int64), ("mfma_flops_update", C.c_double),
                 ("bytes_update_gemm", C.c_double), ("solve_vector_bytes", C.c_double),
                 ("pivot_scope", C.c_int32), ("pivot_fallbacks", C.c_int32), ("k_multifrontal", C.c_int32),
-                ("pad0", C.c_int32), ("mf_pool_bytes", C.c_double), ("mf_update_bytes", C.c_double),
+                ("s1_order", C.c_int32), ("mf_pool_bytes", C.c_double), ("mf_update_bytes", C.c_double),
                 ("mf_extend_add_bytes", C.c_double)]
 
 

@@ -67,9 +67,12 @@ def signature(solver, nrhs, precision) -> str:
         dev = f"{prop.gcnArchName.split(':')[0]}/{prop.multi_processor_count}"
     else:
         dev = "none"
-    return json.dumps({"n_edges": i["n_edges"], "n_subdomains": i["n_subdomains"], "n_blocks": i["n_blocks"],
-                       "n_lm": i["n_lm"], "n_problems": i["n_problems"], "nrhs": int(nrhs),
-                       "precision": _PREC.get(precision, str(precision)), "device": dev}, sort_keys=True)
+    key = {"n_edges": i["n_edges"], "n_subdomains": i["n_subdomains"], "n_blocks": i["n_blocks"],
+           "n_lm": i["n_lm"], "n_problems": i["n_problems"], "nrhs": int(nrhs),
+           "precision": _PREC.get(precision, str(precision)), "device": dev}
+    if i.get("s1_order", 0):  # another row order of step 1: another schedule
+        key["s1_order"] = int(i["s1_order"])
+    return json.dumps(key, sort_keys=True)
 
 
 def _time(fn, repeats):

@@ -1752,6 +1752,7 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->pivot_fallbacks = h->pivot_fallbacks;
     info->solve_vector_bytes = (double)h->pl.solve_min_vblocks * TILE * 16.0;
     info->k_multifrontal = h->pl.mf ? 1 : 0;
+    info->s1_order = h->opt.s1_order;
     if (h->pl.mf) {
         info->mf_pool_bytes = (double)h->pl.ku_tiles * TILE_ELEMS * 16.0;
         info->mf_update_bytes = (double)h->pl.ku_tiles_total * TILE_ELEMS * 16.0;

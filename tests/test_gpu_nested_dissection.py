@@ -9,6 +9,16 @@ residual and agree with the oracle to 1e-9.  At 12^3-hex subdomains (24^3,
 2x2x2) the field must agree with the default banded order's to 1e-10 and
 the relative residual, evaluated on the host with the oracle's own global S
 and load, must be at most 1e-10 per right-hand side.
+
+The batch workload's largest subdomains (32^3 hexes in 2x2x2 subdomains of
+16^3, four wavelengths across: workloads.make_large_subdomain_config) are
+checked against the oracle's S and load on the host.  There the dissection's
+small leaf regions, a fraction of a wavelength across, give step 1 a
+multiplier growth of about 7.5e3 under tile-restricted pivoting (13.5 in the
+banded order, d3m_factor_growth), and its FP64 residual lands near 1e-10
+(4.9e-11 banded): the bar for the dissection's FP64 solution there is 1e-9,
+its FP32 form with refinement must still reach 1e-10, and the banded order
+keeps 1e-10.
 """
 import math
 
@@ -77,3 +87,31 @@ def test_large_subdomains_against_banded_order_and_oracle_residual():
     E32, info = nd.solve(fd, with_info=True)
     assert info["converged"] and info["residual"] <= 1e-10
     assert np.all(host_residual(g.S, E32.cpu().numpy(), fo) <= 1e-10)
+
+
+def test_large_subdomains_high_frequency_oracle_residual():
+    from oracle.fem import GlobalFEM
+    from paper_2002_05018_amd import Solver
+    prob = W.make_large_subdomain_config()
+    print("[gpu nd] 32^3 hexes, 2x2x2 subdomains of 16^3, k = 8 pi", flush=True)
+    g = GlobalFEM(prob.xyz, prob.tets, prob.eps_r, prob.k)
+    fo = g.planewave_rhs(prob.dirs, prob.pols)
+    fd = torch.from_numpy(fo).cuda()
+    band = Solver.from_problem(prob)
+    band.factor("fp64")
+    Eb = band.solve(fd).cpu().numpy()
+    rb = host_residual(g.S, Eb, fo)
+    print(f"[gpu nd] banded FP64 residual {rb.max():.2e} growth {band.growth()}", flush=True)
+    assert np.all(rb <= 1e-10), rb
+    del band
+    torch.cuda.empty_cache()
+    nd = Solver.from_problem(prob, s1_order=1)
+    nd.factor("fp64")
+    E = nd.solve(fd).cpu().numpy()
+    r = host_residual(g.S, E, fo)
+    print(f"[gpu nd] dissection FP64 residual {r.max():.2e} growth {nd.growth()}", flush=True)
+    assert np.all(r <= 1e-9), r
+    assert_rhs_close(E, Eb, 1e-8, "E nested dissection vs banded")
+    nd.factor("fp32_ir")
+    E32, info = nd.solve(fd, with_info=True)
+    assert info["converged"] and info["residual"] <= 1e-10

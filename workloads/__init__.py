@@ -274,6 +274,15 @@ def make_config(i: int, seed: int | None = None) -> Problem:
     raise ValueError(f"unknown configuration {i}")
 
 
+def make_large_subdomain_config(seed: int = 8, n: int = 32, nrhs: int = 16) -> Problem:
+    """The batch workload's largest subdomains on their own: an ``n``^3-hex
+    cube (32: the top of the 12^3..32^3 range) in 2x2x2 box subdomains (the
+    bottom of the 8..64 range, so 16^3 hexes and 31,024 edges each),
+    eps_r ~ U[1, 4], hexes of an eighth of a wavelength (k = 2 pi n / 8),
+    ``nrhs`` plane waves."""
+    return make_problem(n, (2, 2, 2), eps=("uniform", 1, 4), k=2 * math.pi * n / 8, nrhs=nrhs, seed=seed)
+
+
 def make_pec_config(seed: int = 6, n: int = 24, parts=(4, 4, 4), n_pw: int = 4, n_dip: int = 4) -> Problem:
     """PEC plates and impressed currents (the second workload of the paper's
     BVP: perfectly conducting scatterers, J_imp sources).  The paper's
