@@ -192,18 +192,12 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     };
 
     // --------------------------------------------- step 1 (subdomain) plan --
-    if (s1_tree) {
-        // Steps by level of the tile elimination tree of every M_d (parent of
-        // tile column j: the first eliminated row tile below it that is
-        // structurally nonzero): the columns of one level are independent
-        // (none lies in another's structure), so they factor in one step,
-        // and each target tile gathers the pairs of all of its step's
-        // columns in one task.  With a nested-dissection row order the
-        // subtrees of the dissection run side by side; targets in columns of
-        // the next level go first (the next step's pivots need them), the
-        // rest may run on the look-ahead stream.
-        std::vector<std::vector<int>> lev(N);
-        int nl = 0;
+    // levels of the tile elimination tree of every M_d (parent of tile
+    // column j: the first eliminated row tile below it that is structurally
+    // nonzero); used with s1_tree
+    std::vector<std::vector<int>> lev(N);
+    int nl = 0;
+    if (s1_tree)
         for (int d = 0; d < N; ++d) {
             lev[d].assign(pl.TE[d], 0);
             for (int j = 0; j < pl.TE[d]; ++j) {
@@ -214,6 +208,14 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
                 nl = std::max(nl, lev[d][j] + 1);
             }
         }
+    if (s1_tree) {
+        // Steps by level of the tile elimination trees: the columns of one
+        // level are independent (none lies in another's structure), so they
+        // factor in one step, and each target tile gathers the pairs of all
+        // of its step's columns in one task.  With a nested-dissection row
+        // order the subtrees of the dissection run side by side; targets in
+        // columns of the next level go first (the next step's pivots need
+        // them), the rest may run on the look-ahead stream.
         for (int L = 0; L < nl; ++L) {
             FactorStep st;
             st.bk0 = (i64)pl.bk.size();
@@ -679,7 +681,43 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
     }
 
     // S1 forward
-    for (int j = 0; j < maxTE; ++j) {
+    // (s1_tree: by levels of the tile elimination trees, as the
+    // factorisation: a level's diagonal solves, then every row tile below
+    // its columns receives their products in one task)
+    for (int L = 0; L < nl && s1_tree; ++L) {
+        SolveStep st;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int d = 0; d < N; ++d)
+            for (int j = 0; j < pl.TE[d]; ++j) {
+                if (lev[d][j] != L) continue;
+                VDiagTask t{};
+                t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+                t.x = V(V_X, pl.vs1[d] + j); t.y = V(V_Y, pl.vs1[d] + j); t.v = V(V_V, pl.vs1[d] + j);
+                t.acc = -1;
+                t.drow = pl.drow_s1[d] + (i64)j * TILE;
+                t.t = 1; t.n = mrows(d, j);
+                pl.vdiag.push_back(t);
+            }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 0;
+        for (int d = 0; d < N; ++d) {
+            std::vector<int> cols;
+            for (int j = 0; j < pl.TE[d]; ++j)
+                if (lev[d][j] == L) cols.push_back(j);
+            if (cols.empty()) continue;
+            for (int a = cols.front() + 1; a < pl.T[d]; ++a) {
+                const int32_t p0 = (int32_t)pl.vpairs.size();
+                for (int j : cols)
+                    if (j < a && nz[d][a][j]) pl.vpairs.push_back({E(ARR_M, mslot(d, a, j)), V(V_Y, pl.vs1[d] + j)});
+                const int32_t np = (int32_t)pl.vpairs.size() - p0;
+                if (np > 0) pl.vupd.push_back({V(V_X, pl.vs1[d] + a), p0, np});
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.s1_fwd.push_back(st);
+    }
+    for (int j = 0; j < maxTE && !s1_tree; ++j) {
         SolveStep st;
         st.dg0 = (i64)pl.vdiag.size();
         for (int d = 0; d < N; ++d) {
@@ -812,7 +850,42 @@ void build_plan(Plan &pl, const Decomp &dc, const BlockOrder &bo, int unit_max, 
         st.nup = (i64)pl.vupd.size() - st.up0;
         pl.s1_bwd.push_back(st);
     }
-    for (int j = maxTE - 1; j >= 0; --j) {
+    // (s1_tree: by levels from the top, a level's diagonal solves, then each
+    // accumulator below its columns receives their products in one task)
+    for (int L = nl - 1; L >= 0 && s1_tree; --L) {
+        SolveStep st;
+        st.dg0 = (i64)pl.vdiag.size();
+        for (int d = 0; d < N; ++d)
+            for (int j = 0; j < pl.TE[d]; ++j) {
+                if (lev[d][j] != L) continue;
+                VDiagTask t{};
+                t.tt = E(ARR_TT, pl.tt_s1[d] + j);
+                t.x = V(V_X, pl.vs1[d] + j); t.y = -1; t.v = V(V_V, pl.vs1[d] + j);
+                t.acc = V(V_ACC, pl.vs1[d] + j);
+                t.drow = pl.drow_s1[d] + (i64)j * TILE;
+                t.t = 1; t.n = mrows(d, j);
+                pl.vdiag.push_back(t);
+            }
+        st.ndg = (i64)pl.vdiag.size() - st.dg0;
+        st.up0 = (i64)pl.vupd.size();
+        st.up_mode = 2;
+        for (int d = 0; d < N; ++d) {
+            std::vector<int> cols;
+            for (int j = 0; j < pl.TE[d]; ++j)
+                if (lev[d][j] == L) cols.push_back(j);
+            if (cols.empty()) continue;
+            for (int c = 0; c < cols.back(); ++c) {
+                const int32_t p0 = (int32_t)pl.vpairs.size();
+                for (int j : cols)
+                    if (c < j && nz[d][j][c]) pl.vpairs.push_back({E(ARR_M, mslot(d, j, c)), V(V_X, pl.vs1[d] + j)});
+                const int32_t np = (int32_t)pl.vpairs.size() - p0;
+                if (np > 0) pl.vupd.push_back({V(V_ACC, pl.vs1[d] + c), p0, np});
+            }
+        }
+        st.nup = (i64)pl.vupd.size() - st.up0;
+        pl.s1_bwd.push_back(st);
+    }
+    for (int j = maxTE - 1; j >= 0 && !s1_tree; --j) {
         SolveStep st;
         st.dg0 = (i64)pl.vdiag.size();
         for (int d = 0; d < N; ++d) {
