@@ -277,7 +277,7 @@ def bench_batch(args):
 
     probs = W.make_batch_config(count=args.batch_count)
     t0 = time.perf_counter()
-    solver = Solver.batch(probs, probs[0].k, probs[0].alpha, use_graph=True)
+    solver = Solver.batch(probs, probs[0].k, probs[0].alpha, use_graph=True, s1_order=args.s1_order)
     setup_s = time.perf_counter() - t0
     info = solver.info
     f = torch.from_numpy(solver.rhs_planewave_batch(np.stack([p.dirs for p in probs]),
@@ -309,7 +309,8 @@ def bench_batch(args):
                                f"RHS each; one launch per step over all problems, replayed from HIP graphs",
                    "n_problems": len(probs), "n_edges": info["n_edges"], "n_lm": info["n_lm"],
                    "n_blocks": info["n_blocks"], "n_subdomains": info["n_subdomains"],
-                   "nrhs": probs[0].nrhs, "precision": "fp64", "tuning": tuned["tuning"]},
+                   "nrhs": probs[0].nrhs, "precision": "fp64", "tuning": tuned["tuning"],
+                   "step1_rows": "nested dissection" if args.s1_order == 1 else "banded"},
         "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel<double,1> (Schur updates)",
                      "achieved": achieved, "peak": MFMA_PEAK["c128"], "unit": "TFLOP/s",
                      "frac": achieved / MFMA_PEAK["c128"], "traffic": None,

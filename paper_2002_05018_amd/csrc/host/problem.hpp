@@ -105,7 +105,7 @@ struct Decomp {
 // (A_d banded), 1 all edge rows in nested-dissection order
 void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
                          cplx alpha, const double *eps, int s1_order = 0);
-constexpr int kNdLeaf = 192;  // largest region of the dissection left uncut (edges)
+constexpr int kNdLeaf = 1024;  // largest region of the dissection left uncut (edges)
 // Recompute the A_d values for new eps (same pattern).
 void reassemble_values(Decomp &dc, const Mesh &m, double k, const double *eps);
 
