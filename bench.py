@@ -37,9 +37,10 @@ def parse():
                     help="workload: configurations 1-5, pec (24^3 hexes with two PEC plates, plane waves "
                          "and point dipoles) or big (32^3 hexes in 2x2x2 subdomains of 16^3 hexes, the "
                          "batch workload's largest subdomains)")
-    ap.add_argument("--s1-order", type=int, default=0, choices=[0, 1],
-                    help="row order of the subdomain matrices: 0 banded (default), 1 nested dissection "
-                         "(step 1 by levels of the dissection tree; for large subdomains)")
+    ap.add_argument("--s1-order", type=int, default=2, choices=[0, 1, 2],
+                    help="row order of the subdomain matrices: 0 banded, 1 nested dissection (step 1 and "
+                         "its sweeps by levels of the dissection tree), 2 (default) the dissection for "
+                         "subdomains of about 8^3 hexes and more, banded below")
     ap.add_argument("--batch-count", type=int, default=32, help="problems of the configuration 3 batch")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--multifrontal", action="store_true",
@@ -310,7 +311,7 @@ def bench_batch(args):
                    "n_problems": len(probs), "n_edges": info["n_edges"], "n_lm": info["n_lm"],
                    "n_blocks": info["n_blocks"], "n_subdomains": info["n_subdomains"],
                    "nrhs": probs[0].nrhs, "precision": "fp64", "tuning": tuned["tuning"],
-                   "step1_rows": "nested dissection" if args.s1_order == 1 else "banded"},
+                   "step1_rows": "nested dissection" if info["s1_order"] == 1 else "banded"},
         "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel<double,1> (Schur updates)",
                      "achieved": achieved, "peak": MFMA_PEAK["c128"], "unit": "TFLOP/s",
                      "frac": achieved / MFMA_PEAK["c128"], "traffic": None,
@@ -438,9 +439,9 @@ def main():
                    "n_edges": info["n_edges"], "n_lm": info["n_lm"], "n_blocks": info["n_blocks"],
                    "n_subdomains": info["n_subdomains"], "nrhs": nrhs, "precision": "fp64",
                    "step5": "multifrontal" if args.multifrontal else "right-looking",
-                   "step1_rows": "nested dissection" if args.s1_order == 1 else "banded"},
+                   "step1_rows": "nested dissection" if info["s1_order"] == 1 else "banded"},
         "roofline": _roofline(up, info, args.steps, "c128",
-                              None if args.multifrontal or args.s1_order else measured_traffic(args.config, "fp64")),
+                              None if args.multifrontal or info["s1_order"] else measured_traffic(args.config, "fp64")),
         "phases_ms_per_step": dict(phases, note="separate untimed pass with every kernel group timed "
                                                 "(the two streams overlap, so phases do not add up)"),
         "unknowns_per_s": info["n_edges"] / (ms / 1e3),
@@ -480,7 +481,7 @@ def main():
                              "max_rel_diff_vs_fp64": diff,
                              "speedup_vs_fp64": ms / ms32,
                              "roofline": _roofline(up32, info32, args.steps, "c64",
-                                                   None if args.multifrontal or args.s1_order
+                                                   None if args.multifrontal or info["s1_order"]
                                                    else measured_traffic(args.config, "fp32_ir"))}
     if args.multifrontal:
         result["multifrontal"] = {"pool_bytes": info["mf_pool_bytes"], "update_matrix_bytes": info["mf_update_bytes"],

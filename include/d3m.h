@@ -137,9 +137,14 @@ typedef struct {
                              interface edges, each by global id (A_d
                              banded); 1 nested dissection of all its edge
                              rows (geometric bisection, separators after
-                             both sides), the multiplier rows last either
-                             way; the tile pattern follows the fill of the
-                             order chosen                                    */
+                             both sides; step 1 and its solve sweeps run by
+                             levels of the dissection tree); 2 the
+                             dissection when the median subdomain has at
+                             least 4,000 edge rows (about 8^3 hexes), the
+                             banded order otherwise.  The multiplier rows
+                             come last either way; the tile pattern
+                             follows the fill of the order taken
+                             (d3m_info.s1_order)                             */
     int32_t reserved[2];
 } d3m_options;
 
@@ -186,8 +191,9 @@ typedef struct {
     int32_t pivot_fallbacks;  /* factorisations redone with the whole-block
                                  scope (options.pivot_fallback)               */
     int32_t k_multifrontal;   /* 1 when step 5 runs in multifrontal form      */
-    int32_t s1_order;         /* row order of the subdomain matrices
-                                 (options.s1_order)                           */
+    int32_t s1_order;         /* row order the subdomain matrices got: 0
+                                 banded, 1 nested dissection (options.s1_order
+                                 2 resolved)                                  */
     double mf_pool_bytes;     /* device bytes of the update-matrix pool of one
                                  precision (complex128; half for FP32_IR), 0
                                  in the right-looking form                    */

@@ -1142,7 +1142,7 @@ int factor_growth(d3m_problem *h, double &s1, double &k, hipStream_t s) {
 // The plan of a handle: build_plan, then the multifrontal schedule of step 5
 // when the handle's options ask for it.
 void make_plan(Plan &pl, const d3m_problem *h, int scope, int s1_block, int k_block, bool k_fuse) {
-    build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse, h->opt.s1_order == 1);
+    build_plan(pl, h->dc, h->bo, scope == 1 ? 0 : TILE, s1_block, k_block, k_fuse, h->dc.s1_order == 1);
     build_solve_chain(pl);
     if (h->opt.k_multifrontal) build_multifrontal(pl, k_block > 0 ? k_block : 2);
     // loads on PEC edges are ignored: their subdomain rows start from zero
@@ -1203,7 +1203,7 @@ int setup_common(std::unique_ptr<d3m_problem> &h, int64_t nv, const double *xyz,
     if (h->opt.pivot_scope != 0 && h->opt.pivot_scope != 1) return fail(D3M_EINVAL, "pivot_scope must be 0 or 1");
     if (h->opt.k_multifrontal != 0 && h->opt.k_multifrontal != 1)
         return fail(D3M_EINVAL, "k_multifrontal must be 0 or 1");
-    if (h->opt.s1_order != 0 && h->opt.s1_order != 1) return fail(D3M_EINVAL, "s1_order must be 0 or 1");
+    if (h->opt.s1_order < 0 || h->opt.s1_order > 2) return fail(D3M_EINVAL, "s1_order must be 0, 1 or 2");
     try {
         build_mesh(h->mesh, nv, xyz, nt, tets);
         mark_pec(h->mesh, npec, pec);
@@ -1752,7 +1752,7 @@ int d3m_query(d3m_handle h, d3m_info *info) {
     info->pivot_fallbacks = h->pivot_fallbacks;
     info->solve_vector_bytes = (double)h->pl.solve_min_vblocks * TILE * 16.0;
     info->k_multifrontal = h->pl.mf ? 1 : 0;
-    info->s1_order = h->opt.s1_order;
+    info->s1_order = h->dc.s1_order;
     if (h->pl.mf) {
         info->mf_pool_bytes = (double)h->pl.ku_tiles * TILE_ELEMS * 16.0;
         info->mf_update_bytes = (double)h->pl.ku_tiles_total * TILE_ELEMS * 16.0;

@@ -201,10 +201,17 @@ void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
     dc.sub.assign(N, Subdomain());
     {
         std::vector<std::vector<i64>> edges_of(N), tets_of(N);
-        if (s1_order == 1)
-            for (i64 t = 0; t < m.nt; ++t) tets_of[part[t]].push_back(t);
         for (i64 e = 0; e < m.ne; ++e)
             for (i64 s = dc.sub_ptr[e]; s < dc.sub_ptr[e + 1]; ++s) edges_of[dc.sub_list[s]].push_back(e);
+        if (s1_order == 2) {
+            std::vector<i64> sz(N);
+            for (int d = 0; d < N; ++d) sz[d] = (i64)edges_of[d].size();
+            std::nth_element(sz.begin(), sz.begin() + N / 2, sz.end());
+            s1_order = sz[N / 2] >= kNdAutoRows ? 1 : 0;
+        }
+        dc.s1_order = s1_order;
+        if (s1_order == 1)
+            for (i64 t = 0; t < m.nt; ++t) tets_of[part[t]].push_back(t);
         for (int d = 0; d < N; ++d) {
             Subdomain &S = dc.sub[d];
             std::vector<i64> I, B;

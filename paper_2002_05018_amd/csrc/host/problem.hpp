@@ -99,13 +99,19 @@ struct Decomp {
     std::vector<i64> blk_start;          // [nblk + 1]
     i64 n_lm = 0;
     int nblk = 0;
+    int s1_order = 0;                    // row order the subdomain matrices got (0 banded, 1 dissection)
 };
 
 // s1_order: 0 rows of each subdomain [interior | interface] by global id
-// (A_d banded), 1 all edge rows in nested-dissection order
+// (A_d banded), 1 all edge rows in nested-dissection order, 2 the
+// dissection when the median subdomain has at least kNdAutoRows edge rows
+// (the banded order otherwise); the order taken is kept in dc.s1_order
 void build_decomposition(Decomp &dc, const Mesh &m, const i32 *part, double k,
                          cplx alpha, const double *eps, int s1_order = 0);
 constexpr int kNdLeaf = 1024;  // largest region of the dissection left uncut (edges)
+// subdomains of 8^3 hexes (4,184 edges) and more factor faster in the
+// dissection order, those of 6^3 (1,854) in the banded one
+constexpr int kNdAutoRows = 4000;
 // Recompute the A_d values for new eps (same pattern).
 void reassemble_values(Decomp &dc, const Mesh &m, double k, const double *eps);
 

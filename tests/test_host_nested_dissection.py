@@ -74,3 +74,14 @@ def test_factor_schedule_race_free():
     _, s0, s1 = _pair(12, (2, 2, 2))
     n, rep = s1.check_schedule()
     assert n == 0, rep
+
+
+def test_automatic_order_follows_subdomain_size():
+    # s1_order 2: the dissection for subdomains of about 8^3 hexes and more
+    # (median of at least 4,000 edge rows), the banded order below
+    small = Solver.from_problem(W.make_problem(12, (2, 2, 2), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=1, seed=3),
+                                host_only=True, s1_order=2)
+    large = Solver.from_problem(W.make_problem(16, (2, 2, 2), eps=("uniform", 1, 4), k=2 * np.pi, nrhs=1, seed=3),
+                                host_only=True, s1_order=2)
+    assert small.info["s1_order"] == 0 and large.info["s1_order"] == 1
+    assert Solver.from_problem(W.make_config(1), host_only=True).info["s1_order"] == 0
