@@ -485,7 +485,9 @@ int d3m_kernel_stats(d3m_handle h, int kernel, int reset, int64_t *launches,
  *   D3M_EXPORT_EDGES     int64 [n_edges][2] global edges (lo, hi)
  *   D3M_EXPORT_SUB_EDGES int64 [n_d] global edge of each row of subdomain
  *                        `index` in its elimination order ([interior |
- *                        interface])
+ *                        interface], or the nested-dissection order with
+ *                        -1 on the padding rows that start each group at
+ *                        a tile boundary)
  *   D3M_EXPORT_SUB_NI    int64 [1] interior edge count of subdomain `index`
  *   D3M_EXPORT_A_COO     {int64 row, int64 col, double re, double im}[nnz]
  *                        lower triangle of A_d in the subdomain's order
