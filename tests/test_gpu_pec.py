@@ -149,3 +149,18 @@ def test_pec_plates_full_size_against_oracle():
         print(f"[gpu pec] full size {prec}: E vs oracle {err.max():.2e}, residual {r.max():.2e} "
               f"(oracle's own {fx['residual'].max():.2e})", flush=True)
         assert np.all(r <= 1e-10), r
+
+
+@pytest.mark.parametrize("name", ["plates_2x2x2", "plate_2x1x1"])
+def test_pec_with_nested_dissection_rows(name):
+    """PEC identity rows and the dissection's padding rows together."""
+    from paper_2002_05018_amd import Solver
+    p, o, f, Eo, lamo = _oracle(name)
+    s = Solver.from_problem(p, s1_order=1)
+    assert s.info["s1_order"] == 1
+    s.factor("fp64")
+    E, info = s.solve(torch.from_numpy(f).cuda(), with_info=True)
+    E = E.cpu().numpy()
+    assert not np.any(E[:, o.fem.pec])
+    assert_rhs_close(E, Eo, 1e-10, f"{name} E (nested dissection)")
+    assert info["residual"] <= 1e-10
